@@ -1,0 +1,488 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: a published reference vector,
+a closed form, an invariant, a textbook or library routine, or brute force on tiny inputs.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+
+import sc_theory as T
+from oracle import OracleSim, feq, label_mask, lattice, splitmix64, uniform
+from paper_1708_01608_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------------------------------
+# Random field: SplitMix64 (Steele, Lea, Flood 2014) reference outputs for seed 0.
+# ------------------------------------------------------------------------------------------
+def test_splitmix64_reference_vector():
+    with open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) as fh:
+        ref = [int(l, 16) for l in fh if l.strip() and not l.startswith("#")]
+    got = [splitmix64(0, k) for k in range(1, len(ref) + 1)]
+    assert got == ref
+
+
+def test_uniform_is_top_53_bits():
+    for seed, idx in ((1, 0), (7, 12345), (2**63 + 5, 10**9)):
+        u = uniform(seed, idx)
+        assert 0.0 <= u < 1.0
+        assert u == (splitmix64(seed, idx + 1) >> 11) / 2.0**53
+
+
+# ------------------------------------------------------------------------------------------
+# P1: lattice and equilibrium (closed-form moments).
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [9, 19])
+def test_lattice_isotropy(q):
+    e, w = lattice(q)
+    d = 2 if q == 9 else 3
+    e = e[:, :d].astype(float)
+    assert len({tuple(v) for v in e}) == q
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.abs(w @ e).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib->ab", w, e, e) - np.eye(d) / 3.0).max() < 1e-15
+    # fourth-order isotropy: sum w e_a e_b e_c e_d = (d_ab d_cd + d_ac d_bd + d_ad d_bc) / 9
+    I = np.eye(d)
+    iso = (np.einsum("ab,cd->abcd", I, I) + np.einsum("ac,bd->abcd", I, I)
+           + np.einsum("ad,bc->abcd", I, I)) / 9.0
+    assert np.abs(np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e) - iso).max() < 1e-15
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_feq_moments(q):
+    rng = np.random.default_rng(11)
+    e, _ = lattice(q)
+    d = 2 if q == 9 else 3
+    e = e[:, :d].astype(float)
+    for _ in range(50):
+        rho = rng.uniform(0.1, 2.5)
+        u = rng.uniform(-0.06, 0.06, size=d)
+        f = feq(q, rho, u)
+        assert abs(f.sum() - rho) <= 1e-14 * rho
+        assert np.abs(f @ e - rho * u).max() <= 1e-14 * rho
+        # second moment: rho cs^2 I + rho u u
+        P = np.einsum("i,ia,ib->ab", f, e, e)
+        assert np.abs(P - (rho / 3.0 * np.eye(d) + rho * np.outer(u, u))).max() <= 1e-14 * rho
+
+
+# ------------------------------------------------------------------------------------------
+# P4: uniform states are fixed points.
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("q,shape", [(9, (8, 6, 1)), (19, (6, 5, 4))])
+def test_uniform_rest_state_is_fixed_point(q, shape):
+    o = OracleSim(q, *shape, tau=0.9, G=-5.0, amp=0.0)
+    o.set_equilibrium(np.full(o.N, 1.7))
+    f0 = o.get_f()
+    o.step(20)
+    assert np.abs(o.get_f() - f0).max() <= 1e-15
+
+
+@pytest.mark.parametrize("q,shape", [(9, (8, 6, 1)), (19, (6, 5, 4))])
+def test_uniform_flow_is_fixed_point(q, shape):
+    o = OracleSim(q, *shape, tau=1.3, G=-5.0, amp=0.0)
+    u = np.zeros((o.d, o.N))
+    u[0], u[1] = 0.03, -0.02
+    o.set_equilibrium(np.full(o.N, 1.2), u)
+    f0 = o.get_f()
+    o.step(20)
+    assert np.abs(o.get_f() - f0).max() <= 1e-14
+
+
+# ------------------------------------------------------------------------------------------
+# P3: zero net Shan-Chen force on a periodic box; momentum conservation.
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("q,shape", [(9, (48, 40, 1)), (19, (20, 18, 16))])
+def test_zero_net_force_and_momentum(q, shape):
+    rng = np.random.default_rng(3)
+    o = OracleSim(q, *shape, tau=1.0, G=-5.0, amp=0.0)
+    rho = rng.uniform(0.15, 2.0, size=o.N)
+    u = rng.uniform(-0.02, 0.02, size=(o.d, o.N))
+    o.set_equilibrium(rho, u)
+    F = o.force()
+    assert np.abs(F.sum(axis=1)).max() <= 1e-12 * np.abs(F).sum()
+    tot0 = o.totals()
+    o.step(30)
+    tot1 = o.totals()
+    assert abs(tot1[0] - tot0[0]) <= 1e-12 * tot0[0]
+    assert np.abs(tot1[1:] - tot0[1:]).max() <= 1e-12 * tot0[0]
+
+
+# ------------------------------------------------------------------------------------------
+# P2 + P11: mass bookkeeping of the blowing-agent source.
+# ------------------------------------------------------------------------------------------
+def test_mass_equals_initial_plus_spent_budgets():
+    spec = W.two_bubble(nx=64, ny=48, radius=8.0, gap=6, K=25)
+    o = OracleSim(9, spec.nx, spec.ny, 1, spec.tau, spec.G, spec.rho_l, spec.rho_g, spec.amp,
+                  spec.seed, 0.0, spec.K, 8)
+    budgets = np.array([0.02, 0.035])
+    o.seed_nuclei(spec.centres, spec.radii, budgets, 1e-4)
+    tot0 = o.totals()
+    M0 = tot0[0]
+    for _ in range(8):
+        o.step(60)
+        _, rem = o.nuclei()
+        spent = (budgets - rem).sum()
+        tot = o.totals()
+        assert abs(tot[0] - (M0 + spent)) <= 1e-12 * M0
+        # the source adds w_i dm / n_b: zero momentum (sum_i w_i e_i = 0)
+        assert np.abs(tot[1:] - tot0[1:]).max() <= 1e-12 * M0
+    _, rem = o.nuclei()
+    assert np.all(rem <= budgets)
+    assert (budgets - rem).sum() > 0.0
+
+
+def test_budget_bookkeeping_sequence():
+    """B = 2.5e-4 at q = 1e-4 gives 1e-4, 1e-4, 5e-5, 0; nuclei of one bubble pool their rates;
+    a nucleus whose node is liquid gives nothing."""
+    o = OracleSim(9, 40, 24, 1, tau=1.0, G=-5.0, amp=0.0, K=1000)
+    centres = np.array([[10.0, 12.0, 0], [12.0, 12.0, 0], [30.0, 12.0, 0], [20.0, 3.0, 0]])
+    radii = np.array([5.0, 5.0, 5.0, -1.0])  # nuclei 0 and 1 overlap: one bubble
+    budgets = np.array([2.5e-4, 1.0, 2.5e-4, 1.0])
+    o.seed_nuclei(centres, radii, budgets, 1e-4)
+    comp, rem = o.nuclei()
+    assert comp[0] == comp[1] != 0 and comp[2] != 0 and comp[2] != comp[0] and comp[3] == 0
+    # nuclei 0 and 1 share a component from the start: one topological merge at step 0
+    assert o.topo_events() == [dict(step=0, nucleus_a=0, nucleus_b=1)]
+    M = [o.totals()[0]]
+    rems = []
+    for _ in range(4):
+        o.step(1)
+        M.append(o.totals()[0])
+        rems.append(o.nuclei()[1].copy())
+    rems = np.array(rems)
+    np.testing.assert_allclose(rems[:, 0], [1.5e-4, 0.5e-4, 0.0, 0.0], rtol=0, atol=1e-19)
+    np.testing.assert_allclose(rems[:, 2], [1.5e-4, 0.5e-4, 0.0, 0.0], rtol=0, atol=1e-19)
+    np.testing.assert_allclose(rems[:, 1], 1.0 - 1e-4 * np.arange(1, 5), rtol=0, atol=1e-15)
+    assert np.all(rems[:, 3] == 1.0)
+    added = np.diff(M)
+    # atol covers the rounding of the FP64 sum M ~ 1.5e3 itself (ulp ~ 2e-13, 960 terms)
+    np.testing.assert_allclose(added, [3e-4, 3e-4, 2e-4, 1e-4], rtol=0, atol=1e-10)
+
+
+# ------------------------------------------------------------------------------------------
+# Streaming direction: a density wave in a uniform flow (G = 0) is carried downstream.
+# rho_k(t) = eps exp(-i k U t) cos(k cs t) for the two sound modes U +- cs, so the phase of the
+# density mode advances by -k U t whatever the sign of cos(k cs t).
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("q,shape", [(9, (64, 4, 1)), (19, (64, 4, 4))])
+@pytest.mark.parametrize("U", [0.05, -0.08])
+def test_density_wave_is_advected_with_the_flow(q, shape, U):
+    o = OracleSim(q, *shape, tau=1.0, G=0.0, rho_l=1.0, rho_g=1.0, amp=0.0, K=0)
+    nx = shape[0]
+    x = np.arange(o.N) % nx
+    k = 2 * math.pi / nx
+    u = np.zeros((o.d, o.N))
+    u[0] = U
+    o.set_equilibrium(1.0 + 0.01 * np.cos(k * x), u)
+    t = 60
+    o.step(t)
+    rho, _, _ = o.fields()
+    mode = np.mean((rho - 1.0) * np.exp(-1j * k * x))
+    phase = np.angle(mode * np.sign(math.cos(k * t / math.sqrt(3.0))))
+    assert abs(phase - (-k * U * t)) < 0.02
+
+
+# ------------------------------------------------------------------------------------------
+# P5: lattice Laplacian of the EOS pressure (closed-form eigenvalue; G = 0 makes p = rho/3).
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("q,shape,k", [(9, (16, 12, 1), (2, 1, 0)), (9, (16, 12, 1), (5, 3, 0)),
+                                       (19, (8, 10, 6), (1, 2, 1)), (19, (8, 10, 6), (3, 4, 2))])
+def test_pressure_laplacian_eigenvalue(q, shape, k):
+    o = OracleSim(q, *shape, G=0.0, amp=0.0)
+    nx, ny, nz = shape
+    idx = np.arange(o.N)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    kv = (2 * math.pi * k[0] / nx, 2 * math.pi * k[1] / ny, 2 * math.pi * k[2] / nz)
+    phase = kv[0] * x + kv[1] * y + kv[2] * z
+    amp = 0.1
+    o.set_equilibrium(1.0 + amp * np.cos(phase))
+    p, lap = o.laplacian_p()
+    lam = T.laplacian_eigenvalue(q, kv)
+    np.testing.assert_allclose(p, (1.0 + amp * np.cos(phase)) / 3.0, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(lap, lam * amp * np.cos(phase) / 3.0, rtol=0, atol=2e-15)
+
+
+# ------------------------------------------------------------------------------------------
+# P6: flat-interface coexistence against the mechanical-stability condition.
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("G", [-4.5, -5.0, -5.5])
+def test_flat_interface_coexistence(G):
+    rg, rl, _ = T.coexistence(G)
+    mg, ml = T.maxwell(G)
+    nx, ny = 128, 4
+    o = OracleSim(9, nx, ny, 1, tau=1.0, G=G, rho_l=rl, rho_g=rg, amp=0.0, K=0)
+    x = np.arange(nx)
+    o.set_equilibrium(np.tile(np.where((x >= 32) & (x < 96), rl, rg), ny))
+    o.step(40000)
+    r1, _, _ = o.fields()
+    o.step(1000)
+    r2, _, _ = o.fields()
+    assert np.abs(r2 - r1).max() < 1e-7  # converged
+    liquid, gas = r2[64], r2[0]
+    assert abs(liquid / rl - 1) < 2e-3
+    assert abs(gas / rg - 1) < 1.5e-2
+    # the scheme follows mechanical stability, not the equal-area rule
+    assert abs(gas - rg) < 0.5 * abs(gas - mg)
+
+
+def test_flat_interface_3d_matches_2d():
+    G = -5.0
+    rg, rl, _ = T.coexistence(G)
+    o = OracleSim(19, 64, 4, 4, tau=1.0, G=G, rho_l=rl, rho_g=rg, amp=0.0, K=0)
+    x = np.arange(64)
+    o.set_equilibrium(np.tile(np.where((x >= 16) & (x < 48), rl, rg), 16))
+    o.step(12000)
+    r, _, _ = o.fields()
+    assert abs(r[32] / rl - 1) < 2e-3
+    assert abs(r[0] / rg - 1) < 1.5e-2
+
+
+# ------------------------------------------------------------------------------------------
+# P7: Laplace's law on static 2D bubbles.
+# ------------------------------------------------------------------------------------------
+def test_laplace_law_2d():
+    G = -5.0
+    rg, rl, _ = T.coexistence(G)
+    n = 96
+    inv_r, dp = [], []
+    for R in (14, 17, 20, 24, 28):
+        o = OracleSim(9, n, n, 1, tau=1.0, G=G, rho_l=rl, rho_g=rg, amp=0.0, K=0)
+        xx, yy = np.meshgrid(np.arange(n), np.arange(n))
+        r2 = (xx - n / 2 + 0.5) ** 2 + (yy - n / 2 + 0.5) ** 2
+        o.set_equilibrium(np.where(r2 <= R * R, rg, rl).reshape(-1))
+        o.step(10000)
+        rho, _, _ = o.fields()
+        p = T.pressure(rho, G).reshape(n, n)
+        r = rho.reshape(n, n)
+        rin, rout = r[n // 2, n // 2], r[0, 0]
+        reff = math.sqrt((rout * n * n - rho.sum()) / (math.pi * (rout - rin)))
+        assert 0.6 * R < reff < 1.1 * R  # the bubble survived (it shrinks to its Laplace size)
+        inv_r.append(1.0 / reff)
+        dp.append(p[n // 2, n // 2] - p[0, 0])
+    A = np.vstack([inv_r, np.ones(len(inv_r))]).T
+    (sigma, icpt), *_ = np.linalg.lstsq(A, np.array(dp), rcond=None)
+    pred = A @ np.array([sigma, icpt])
+    r2 = 1 - ((np.array(dp) - pred) ** 2).sum() / ((np.array(dp) - np.mean(dp)) ** 2).sum()
+    assert sigma > 0
+    assert r2 >= 0.999
+    assert abs(icpt) <= 0.05 * max(dp)
+
+
+# ------------------------------------------------------------------------------------------
+# P8: BGK shear-wave decay (G = 0), nu = (tau - 1/2)/3.
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("q,shape", [(9, (4, 128, 1)), (19, (4, 128, 4))])
+@pytest.mark.parametrize("tau", [0.8, 1.0, 1.4])
+def test_shear_wave_viscosity(q, shape, tau):
+    o = OracleSim(q, *shape, tau=tau, G=0.0, rho_l=1.0, rho_g=1.0, amp=0.0, K=0)
+    nx, ny, _ = shape
+    y = (np.arange(o.N) // nx) % ny
+    k = 2 * math.pi / ny
+    u = np.zeros((o.d, o.N))
+    u[0] = 1e-3 * np.sin(k * y)
+    o.set_equilibrium(np.ones(o.N), u)
+
+    def amplitude():
+        _, uu, _ = o.fields()
+        return 2 * np.mean(uu[0] * np.sin(k * y))
+
+    o.step(100)
+    a1 = amplitude()
+    o.step(400)
+    a2 = amplitude()
+    rate = math.log(a1 / a2) / 400.0
+    nu = (tau - 0.5) / 3.0
+    assert abs(rate / (nu * k * k) - 1) < (1e-6 if tau == 1.0 else 1e-3)
+
+
+# ------------------------------------------------------------------------------------------
+# P9: merge criterion sign against the spinodal closed form (static synthetic films).
+# ------------------------------------------------------------------------------------------
+def _film_box(rho_c, film_len=5, curvature=0.01, pocket=False, G=-5.0):
+    """Two gas slabs (x = 10..20 and x = 21+film_len..31+film_len, all y) around a liquid film
+    with a symmetric parabolic density peak rho_c; 64 x 16 D2Q9 box, rho_g = 0.16, rho_l = 1.93
+    elsewhere.  Returns (sim, film x range)."""
+    nx, ny = 64, 16
+    o = OracleSim(9, nx, ny, 1, tau=1.0, G=G, amp=0.0, K=0)
+    a0, a1 = 10, 20
+    b0 = a1 + 1 + film_len
+    b1 = b0 + 10
+    x = np.arange(nx)
+    mid = (a1 + 1 + b0 - 1) / 2.0
+    prof = np.full(nx, 1.93)
+    prof[a0:a1 + 1] = 0.16
+    prof[b0:b1 + 1] = 0.16
+    film = np.arange(a1 + 1, b0)
+    prof[film] = rho_c - curvature * (film - mid) ** 2
+    rho = np.tile(prof, (ny, 1))
+    if pocket:
+        rho[:, int(mid)] = 0.16  # a gas sheet inside the film (not a bubble)
+    centres = np.array([[15.0, 8.0, 0.0], [(b0 + b1) / 2.0, 8.0, 0.0]])
+    o.seed_nuclei(centres, np.array([-1.0, -1.0]), np.zeros(2), 0.0)
+    o.set_equilibrium(rho.reshape(-1))
+    return o, film
+
+
+@pytest.mark.parametrize("rho_c", [1.10, 1.20, 1.24, 1.33, 1.40, 1.60, 1.90])
+def test_criterion_sign_follows_upper_spinodal(rho_c):
+    G = -5.0
+    _, hi = T.spinodals(G)
+    o, film = _film_box(rho_c, G=G)
+    assert o.test_pass() == 0
+    ev = o.events()
+    # closed form: at a symmetric density peak, lap p = p'(rho_c) lap rho, lap rho < 0
+    expect_fire = rho_c < hi
+    assert (len(ev) == 1) == expect_fire
+    # p at the centre and its lattice Laplacian from the full-field output agree in sign
+    _, lap = o.laplacian_p()
+    c = 8 * 64 + 23
+    assert (lap[c] >= 0) == expect_fire
+    if ev:
+        e = ev[0]
+        assert e["film_len"] == len(film) == 5
+        assert e["film_node"] % 64 == 23  # densest node of the run
+        assert e["nucleus_a"] == 0 and e["nucleus_b"] == 1
+        assert e["lap_p"] == pytest.approx(lap[e["film_node"]], rel=1e-12)
+
+
+def test_criterion_skips_long_and_interrupted_films():
+    o, _ = _film_box(1.10, film_len=9, curvature=0.002)  # longer than film_max = 8
+    o.test_pass()
+    assert o.events() == []
+    o, _ = _film_box(1.10, film_len=7, curvature=0.002, pocket=True)  # another label inside
+    o.test_pass()
+    assert o.events() == []
+    o, _ = _film_box(1.10, film_len=8, curvature=0.002)  # exactly film_max fires
+    o.test_pass()
+    assert len(o.events()) == 1 and o.events()[0]["film_len"] == 8
+
+
+def test_criterion_fires_once_per_pair():
+    o, _ = _film_box(1.10)
+    o.test_pass()
+    o.test_pass()
+    assert len(o.events()) == 1
+
+
+# ------------------------------------------------------------------------------------------
+# P10: canonical periodic labelling against brute force.
+# ------------------------------------------------------------------------------------------
+def _periodic_adjacency(q, shape):
+    nx, ny, nz = shape
+    e, _ = lattice(q)
+    N = nx * ny * nz
+    idx = np.arange(N)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    rows, cols = [], []
+    for v in e:
+        if not v.any():
+            continue
+        j = ((x + v[0]) % nx) + nx * (((y + v[1]) % ny) + ny * ((z + v[2]) % nz))
+        rows.append(idx)
+        cols.append(j)
+    return np.concatenate(rows), np.concatenate(cols)
+
+
+def _canonical_from_components(mask, ncomp_labels):
+    out = np.zeros(mask.size, dtype=np.uint32)
+    for c in np.unique(ncomp_labels[mask]):
+        members = np.nonzero(mask & (ncomp_labels == c))[0]
+        out[members] = members.min() + 1
+    return out
+
+
+def test_labels_exhaustive_4x4_periodic():
+    """All 2^16 masks of a periodic 4x4 D2Q9 box against a transitive closure."""
+    rows, cols = _periodic_adjacency(9, (4, 4, 1))
+    A = np.zeros((16, 16), dtype=np.int32)
+    A[rows, cols] = 1
+    masks = ((np.arange(1 << 16)[:, None] >> np.arange(16)[None, :]) & 1).astype(np.int32)
+    Am = A[None] * masks[:, :, None] * masks[:, None, :] + np.eye(16, dtype=np.int32)[None]
+    R = Am
+    for _ in range(4):  # (I + A)^16 reaches every node of a component
+        R = (np.einsum("bij,bjk->bik", R, R) > 0).astype(np.int32)
+    first = np.argmax(R > 0, axis=2)  # smallest reachable index
+    ref = np.where(masks > 0, first + 1, 0).astype(np.uint32)
+    bad = 0
+    for m in range(1 << 16):
+        lab, n = label_mask(9, (4, 4, 1), masks[m])
+        if not np.array_equal(lab, ref[m]) or n != len(np.unique(ref[m][ref[m] > 0])):
+            bad += 1
+    assert bad == 0
+
+
+@pytest.mark.parametrize("q,shape", [(19, (8, 8, 8)), (19, (6, 9, 5)), (9, (17, 11, 1)),
+                                     (9, (32, 32, 1))])
+@pytest.mark.parametrize("fill", [0.1, 0.3, 0.45, 0.6])
+def test_labels_random_masks_vs_scipy(q, shape, fill):
+    rng = np.random.default_rng(int(fill * 100) + shape[0])
+    N = shape[0] * shape[1] * shape[2]
+    rows, cols = _periodic_adjacency(q, shape)
+    for _ in range(5):
+        mask = rng.random(N) < fill
+        keep = mask[rows] & mask[cols]
+        g = coo_matrix((np.ones(keep.sum()), (rows[keep], cols[keep])), shape=(N, N))
+        _, comp = connected_components(g, directed=False)
+        ref = _canonical_from_components(mask, comp)
+        lab, n = label_mask(q, shape, mask.astype(np.uint8))
+        assert np.array_equal(lab, ref)
+        assert n == len(np.unique(ref[ref > 0]))
+
+
+def test_labels_wrap_around_spiral():
+    """A band that crosses both periodic seams is one component labelled by its smallest index."""
+    nx, ny = 12, 10
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    mask[3, :] = 1           # row crossing the x seam
+    mask[:, 7] = 1           # column crossing the y seam
+    mask[8, 9] = 1           # diagonal neighbour of (7, 7)? no: isolated node
+    lab, n = label_mask(9, (nx, ny, 1), mask.reshape(-1))
+    lab = lab.reshape(ny, nx)
+    assert n == 2
+    assert lab[3, 0] == lab[0, 7] == lab[9, 7] == 0 * nx + 7 + 1
+    assert lab[8, 9] == 8 * nx + 9 + 1
+
+
+# ------------------------------------------------------------------------------------------
+# Painted bubbles, nucleus map and statistics (brute force).
+# ------------------------------------------------------------------------------------------
+def test_two_bubble_paint_and_statistics():
+    spec = W.two_bubble()
+    o = OracleSim(9, spec.nx, spec.ny, 1, spec.tau, spec.G, spec.rho_l, spec.rho_g, spec.amp,
+                  spec.seed, 0.0, spec.K, 8)
+    o.seed_nuclei(spec.centres, spec.radii, spec.budgets, 0.0)
+    xx, yy = np.meshgrid(np.arange(128), np.arange(128))
+    bub = o.bubbles()
+    assert len(bub) == 2
+    for b, c in zip(bub, spec.centres):
+        disc = ((xx - c[0]) ** 2 + (yy - c[1]) ** 2 <= 15.0 ** 2).reshape(-1)
+        assert b["n"] == disc.sum() == 716
+        assert b["label"] == np.nonzero(disc)[0].min() + 1
+        assert b["centroid"][0] == c[0] and b["centroid"][1] == c[1]
+        assert b["radius"] == pytest.approx(math.sqrt(716 / math.pi), rel=1e-15)
+    row = o.labels().reshape(128, 128)[63]
+    assert np.all(row[62:66] == 0) and row[61] != 0 and row[66] != 0  # the 4-node film
+
+
+# ------------------------------------------------------------------------------------------
+# P12: mirror symmetry of the noiseless two-bubble box.
+# ------------------------------------------------------------------------------------------
+def test_two_bubble_mirror_symmetry():
+    spec = W.two_bubble(amp=0.0)
+    o = OracleSim(9, spec.nx, spec.ny, 1, spec.tau, spec.G, spec.rho_l, spec.rho_g, 0.0,
+                  spec.seed, 0.0, 0, 8)
+    o.seed_nuclei(spec.centres, spec.radii, spec.budgets, 0.0)
+    o.step(200)
+    rho, u, _ = o.fields()
+    r = rho.reshape(128, 128)
+    ux, uy = u[0].reshape(128, 128), u[1].reshape(128, 128)
+    assert np.abs(r - r[:, ::-1]).max() < 1e-13
+    assert np.abs(r - r[::-1, :]).max() < 1e-13
+    assert np.abs(ux + ux[:, ::-1]).max() < 1e-13
+    assert np.abs(uy + uy[::-1, :]).max() < 1e-13

@@ -1,0 +1,213 @@
+"""Benchmark of the Shan-Chen hot path on one MI355X: MLUPS and the fraction of the HBM roofline.
+
+A "step" of this benchmark is one test period of the workload: K lattice time steps (fused
+stream-collide kernel + blowing-agent source) followed by the test pass (gas labelling, bubble
+statistics, FP64 EOS/Laplacian merge criterion, FP64 totals), i.e. one pass of every part of the
+hot path.  Inputs (the populations) are resident in HBM before timing starts.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload foam_3d] [--storage f32]
+                  [--compute auto] [--variants]
+
+Prints one JSON line.  `value` is MLUPS (million lattice-node updates per second) of the whole
+job; `roofline` is the step kernel's algorithmic bytes per launch over its HIP-event-measured
+average duration on the simulation stream, against the 8 TB/s HBM peak; `cpu_baseline` is the
+FP64 CPU oracle timed on a bounded sample of the same workload on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = ("foam_3d", "foam_2d", "two_bubble", "foam_3d_large")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="foam_3d", choices=WORKLOADS)
+    ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
+    ap.add_argument("--compute", default="auto", choices=("auto", "f32", "f64"))
+    ap.add_argument("--tile", default=None, help="tx,ty,tz of the step kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=0,
+                    help="oracle steps timed for cpu_baseline (0: pick ~10-30 s)")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time FP32-compute / 16-bit storage variants (extra JSON lines)")
+    return ap.parse_args()
+
+
+def workload_spec(name):
+    from paper_1708_01608_amd import workloads as W
+
+    return {"foam_3d": W.foam_3d, "foam_2d": W.foam_2d, "two_bubble": W.two_bubble,
+            "foam_3d_large": W.foam_3d_large}[name]()
+
+
+def bytes_per_node(q, storage):
+    return 2 * q * (4 if storage == "f32" else 2)
+
+
+def step_kernel_hash():
+    h = hashlib.sha256()
+    for f in ("sc_step.hip", "sc_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1708_01608_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, storage, compute, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current step kernel; else None."""
+    path = os.path.join(ROOT, "profiles", f"step_counters_{workload}_{storage}_{compute}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != step_kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_gpu(spec, args, storage, compute, steps, warmup, tile=None):
+    import torch
+
+    from paper_1708_01608_amd import sc
+
+    sim = sc.Sim.from_spec(spec, storage=storage, compute=compute, tile=tile)
+    sim.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
+    K = spec.K
+    for _ in range(warmup):
+        sim.step(K)
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step(K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms, launches = sim.profile_read(sc.SC_KERNEL_STEP)
+    src_ms, src_n = sim.profile_read(sc.SC_KERNEL_SOURCE)
+    test_ms, test_n = sim.profile_read(sc.SC_KERNEL_TEST)
+    sim.profile(False)
+    tile_used = sim.step_config()
+    comp = sim.compute_type()
+    sim.close()
+    return dict(wall=wall, step_ms=step_ms, launches=launches, src_ms=src_ms, src_n=src_n,
+                test_ms=test_ms, test_n=test_n, tile=tile_used, compute=comp)
+
+
+def cpu_baseline(spec, sample_steps):
+    from oracle import OracleSim, num_threads
+
+    o = OracleSim(spec.q, spec.nx, spec.ny, spec.nz, spec.tau, spec.G, spec.rho_l, spec.rho_g,
+                  spec.amp, spec.seed, spec.theta, 0, spec.film_max)
+    o.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
+    if sample_steps <= 0:
+        t0 = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t0
+        sample_steps = int(max(1, min(2000, 15.0 / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(sample_steps)
+    dt = time.perf_counter() - t0
+    return dict(value=round(spec.N * sample_steps / dt / 1e6, 3), unit="MLUPS",
+                cores=num_threads(), kind="oracle",
+                sample=f"{spec.name} {spec.nx}x{spec.ny}x{spec.nz}, {sample_steps} oracle steps "
+                       f"(FP64 collide-stream + source; test passes off), {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU path (slab "
+                                   "domain decomposition) is a design note, not code",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    from paper_1708_01608_amd import sc
+
+    if not os.path.exists(sc.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    spec = workload_spec(args.workload)
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    r = run_gpu(spec, args, args.storage, args.compute, args.steps, args.warmup, tile)
+    lattice_steps = args.steps * spec.K
+    mlups = spec.N * lattice_steps / r["wall"] / 1e6
+    bpn = bytes_per_node(spec.q, args.storage)
+    bytes_per_launch = bpn * spec.N
+    avg_s = r["step_ms"] / 1e3 / max(r["launches"], 1)
+    achieved = bytes_per_launch / avg_s / 1e9
+    traffic = traffic_from_profile(args.workload, args.storage, r["compute"], bytes_per_launch)
+    out = {
+        "metric": "Shan-Chen MLUPS & % of HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["wall"] * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": r["compute"] if args.storage == "f32" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": spec.name,
+            "lattice": f"D{spec.d}Q{spec.q}",
+            "box": [spec.nx, spec.ny, spec.nz],
+            "nodes": spec.N,
+            "nuclei": int(len(spec.radii)),
+            "storage": args.storage,
+            "compute": r["compute"],
+            "tau": spec.tau,
+            "G": spec.G,
+            "test_every": spec.K,
+            "lattice_steps_per_step": spec.K,
+            "step_tile": list(r["tile"]),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_step3d" if spec.q == 19 else "k_step2d",
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": round(avg_s * 1e6, 2),
+            "launches": r["launches"],
+        },
+        "breakdown_ms": {
+            "step_kernel": round(r["step_ms"], 3),
+            "source": round(r["src_ms"], 3),
+            "test_pass": round(r["test_ms"], 3),
+            "wall": round(r["wall"] * 1e3, 3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+    if args.variants:
+        for storage, compute in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
+            rv = run_gpu(spec, args, storage, compute, args.steps, args.warmup, tile)
+            b = bytes_per_node(spec.q, storage) * spec.N
+            a = b / (rv["step_ms"] / 1e3 / max(rv["launches"], 1)) / 1e9
+            print(json.dumps({"variant": f"{storage} storage / {compute} compute",
+                              "workload": spec.name,
+                              "MLUPS": round(spec.N * lattice_steps / rv["wall"] / 1e6, 1),
+                              "step_kernel_GBps": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
+                              "avg_launch_us": round(rv["step_ms"] * 1e3 / max(rv["launches"], 1), 2)}),
+                  flush=True)
+
+
+if __name__ == "__main__":
+    main()

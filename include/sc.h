@@ -1,0 +1,200 @@
+/*
+ * sc.h -- C ABI of the MI355X (gfx950) Shan-Chen bubble growth / merging library (libsc.so).
+ *
+ * Paper: Barzegari, Bayani, Mirbagheri, "A criterion for bubble merging in liquid metal:
+ * computational and experimental study" (arXiv 1708.01608).  The calls follow its problem
+ * statement: nucleation sites with a blowing agent decomposed at them and liquid elsewhere
+ * (Sec. 3.1), a Shan-Chen pseudopotential step per time step (Sec. 3.1, Fig. 1 step 6), gas added
+ * to every bubble until the agent is spent (Sec. 3), new bubble sizes (Fig. 1 step 7), and the
+ * film-rupture switch decided by the second derivative of pressure (Sec. 3.1 eta_m, Sec. 4).
+ *
+ * Conventions for every call:
+ *  - Lattice units; periodic box nx * ny * nz, linear node index idx = x + nx * (y + ny * z), x
+ *    fastest.  D2Q9 needs nz == 1; every axis is >= 4 nodes.
+ *  - Host arrays passed in are borrowed for the duration of the call; output pointers that are
+ *    NULL skip that output.  Calls are synchronous: they return after the work on the
+ *    simulation's stream has completed.  One thread at a time per sc_sim.
+ *  - Every call returns an sc_status.  SC_E_INVAL leaves the state unchanged.  After
+ *    SC_E_DEVICE (a HIP error) or SC_E_NUMERIC (a non-finite FP64 total) the handle is latched:
+ *    every later call except sc_destroy returns SC_E_STATE.  sc_last_error() gives the message
+ *    of the calling thread's last failure.
+ *  - The library owns the sc_sim, its device memory (obtained through sc_params.allocator, or
+ *    hipMalloc when NULL) and its stream when it created one.
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SC_ABI_VERSION 1u
+
+typedef enum sc_status {
+    SC_OK = 0,
+    SC_E_INVAL = -1,       /* invalid argument; nothing changed */
+    SC_E_NOMEM = -2,       /* device allocation failed */
+    SC_E_DEVICE = -3,      /* a HIP call failed (handle latched) */
+    SC_E_STATE = -4,       /* handle latched by an earlier failure, or call out of order */
+    SC_E_NUMERIC = -5,     /* a global FP64 total was not finite (handle latched) */
+    SC_E_UNSUPPORTED = -6  /* valid request this build does not provide */
+} sc_status;
+
+enum { SC_D2Q9 = 9, SC_D3Q19 = 19 };
+
+/* Population storage.  Populations are stored as deviations f_i - w_i rho_ref (the paper leaves
+ * precision open; the shift keeps the stored magnitudes small where the density is near
+ * rho_ref). */
+enum { SC_STORE_F32 = 0, SC_STORE_F16 = 1, SC_STORE_BF16 = 2 };
+
+/* Arithmetic of the step kernel.  AUTO: FP64 on FP32 storage, FP32 on 16-bit storage.  FP64
+ * arithmetic is offered on FP32 storage only (SC_E_UNSUPPORTED otherwise). */
+enum { SC_COMPUTE_AUTO = 0, SC_COMPUTE_F32 = 1, SC_COMPUTE_F64 = 2 };
+
+/* Device memory callbacks (PyTorch's caching allocator from Python, or any C allocator).
+ * alloc returns NULL on failure; free receives exactly what alloc returned. */
+typedef struct sc_allocator {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} sc_allocator;
+
+typedef struct sc_params {
+    uint32_t abi_version;      /* must equal SC_ABI_VERSION */
+    int32_t lattice;           /* SC_D2Q9 or SC_D3Q19 */
+    int32_t nx, ny, nz;        /* periodic box; nz == 1 for D2Q9 */
+    double tau;                /* BGK relaxation time, > 0.5 */
+    double G;                  /* Shan-Chen strength (Sec. 3.1); G < 0 attracts */
+    double rho_liquid;         /* fill density of every node (Sec. 3.1 "liquid") */
+    double rho_gas;            /* density painted inside nuclei */
+    double noise_amp;          /* additive U[-amp, amp] density noise on every node */
+    uint64_t noise_seed;       /* SplitMix64 seed of the noise: U = (idx+1)-th output of the stream */
+    double gas_threshold;      /* gas iff rho < threshold; <= 0 selects (rho_liquid + rho_gas)/2 */
+    int32_t test_every;        /* K: labelling + merge test after every K-th step; 0 = never */
+    int32_t film_max;          /* longest liquid run (nodes) still tested as a film; >= 1 */
+    int32_t storage;           /* SC_STORE_F32 / F16 / BF16 */
+    int32_t compute;           /* SC_COMPUTE_AUTO / F32 / F64 */
+    double rho_ref;            /* storage shift; < 0 selects 0 for F32 and rho_liquid for 16-bit */
+    void* stream;              /* hipStream_t to run on; NULL: the library creates one */
+    const sc_allocator* allocator; /* NULL: hipMalloc / hipFree */
+    int32_t tile_x, tile_y, tile_z; /* step-kernel tile; 0 selects the tuned default */
+    int32_t reserved1;
+} sc_params;
+
+/* One firing of the merge criterion (Sec. 3.1 eta_m: 1 -> 0; Sec. 4 film rupture). */
+typedef struct sc_merge_event {
+    int64_t step;              /* time step of the test pass that fired */
+    int32_t nucleus_a;         /* smallest nucleus index of each bubble (stable bubble ids) */
+    int32_t nucleus_b;
+    uint32_t label_a;          /* component labels at that pass, label_a < label_b */
+    uint32_t label_b;
+    int64_t film_node;         /* linear index of the film-centre node c* */
+    int32_t film_len;          /* liquid nodes on the film run */
+    int32_t reserved;
+    double lap_p;              /* FP64 lattice Laplacian of p at c* (fired: >= 0) */
+    double rho_film;           /* FP64 density at c* */
+} sc_merge_event;
+
+/* Two nucleus groups found in one gas component for the first time (topological merge). */
+typedef struct sc_topo_event {
+    int64_t step;
+    int32_t nucleus_a;         /* group representatives (smallest nucleus index), a < b */
+    int32_t nucleus_b;
+} sc_topo_event;
+
+/* Statistics of one bubble at the last test pass (Fig. 1 step 7, "new bubbles' size"). */
+typedef struct sc_bubble {
+    uint32_t label;            /* 1 + smallest linear index of the component */
+    int32_t nucleus;           /* smallest nucleus index in the bubble */
+    int64_t n;                 /* gas node count */
+    double centroid[3];        /* anchor node + mean integer minimal-image offset */
+    double radius;             /* sqrt(n/pi) (2D) or cbrt(3n/(4 pi)) (3D) */
+    int32_t n_nuclei;
+    int32_t reserved;
+} sc_bubble;
+
+/* Kernel classes for sc_profile_read. */
+enum { SC_KERNEL_STEP = 0, SC_KERNEL_SOURCE = 1, SC_KERNEL_TEST = 2 };
+
+uint32_t sc_abi_version(void);
+const char* sc_last_error(void);
+
+/* Fills *p with the defaults (abi_version set, D2Q9 128x128, tau 1, G -5, densities 1.93 / 0.16,
+ * noise 1e-3 seed 1, K = 10, film_max = 8, FP32 storage, automatic compute type).
+ * SC_E_INVAL if p is NULL. */
+int sc_params_init(sc_params* p);
+
+/* Sec. 3.1: every node is liquid, rho = rho_liquid + amp (2U - 1), f = f_eq(rho, 0).
+ * Errors: SC_E_INVAL (bad parameters, *out untouched), SC_E_NOMEM, SC_E_DEVICE. */
+int sc_create(const sc_params* p, struct sc_sim** out);
+int sc_destroy(struct sc_sim* sim);
+
+/* Sec. 3.1: nucleation sites and the blowing agent decomposed at them.  centre is [n][3] (z
+ * ignored in 2D); nodes whose minimal-image distance to a centre is <= its radius become gas,
+ * rho = rho_gas + amp (2U - 1), f = f_eq(rho, 0) (a negative radius registers the nucleus
+ * without painting); budget[k] is the agent mass of nucleus k; rate is the mass each nucleus
+ * gives per step while its budget lasts (Sec. 3).  Replaces any earlier nuclei and runs a test
+ * pass (labels and bubble statistics, no merge criterion) at the current step.
+ * Errors: SC_E_INVAL (n < 0, NULL arrays with n > 0, rate < 0, non-finite values). */
+int sc_seed_nuclei(struct sc_sim* sim, int32_t n, const double* centre, const double* radius,
+                   const double* budget, double rate);
+
+/* Advances nsteps time steps (Fig. 1): pseudopotential, Shan-Chen force, forced BGK collision and
+ * pull streaming in one fused kernel; then the blowing-agent source on the gas nodes of every
+ * bubble; after every K-th step a test pass (gas labelling, bubble statistics, merge criterion,
+ * FP64 totals).  nsteps >= 0.  SC_E_NUMERIC if a total is not finite. */
+int sc_step(struct sc_sim* sim, int32_t nsteps);
+
+/* rho[N] and u[d][N] = (j + F/2)/rho (FP32), totals = (M, Jx, Jy, Jz) summed in FP64 over the
+ * post-streaming populations in a fixed order. */
+int sc_fields(struct sc_sim* sim, float* rho, float* u, double* totals);
+
+/* Sec. 3.1 EOS and the criterion's operator, in FP64: p = rho/3 + (G/6) psi^2 and
+ * lap[x] = 6 sum_{i != 0} w_i (p(x + e_i) - p(x)). */
+int sc_laplacian_p(struct sc_sim* sim, double* p, double* lap);
+
+/* Canonical labels of a gas mask: label = 1 + smallest linear index of the component, 0 for
+ * liquid; connectivity = the lattice neighbours (8 in 2D, 18 in 3D), periodic.  mask[N] (nonzero =
+ * gas) or NULL for rho < gas_threshold on the current state.  *ncomp receives the component
+ * count.  Does not change the bubble registry. */
+int sc_label_bubbles(struct sc_sim* sim, const uint8_t* mask, uint32_t* labels, int64_t* ncomp);
+
+/* Registry of the last test pass and of all passes so far.  *n_total receives the full count;
+ * at most cap entries are copied. */
+int sc_merge_events(struct sc_sim* sim, sc_merge_event* out, int32_t cap, int32_t* n_total);
+int sc_topo_events(struct sc_sim* sim, sc_topo_event* out, int32_t cap, int32_t* n_total);
+int sc_bubbles(struct sc_sim* sim, sc_bubble* out, int32_t cap, int32_t* n_total);
+int sc_last_labels(struct sc_sim* sim, uint32_t* labels);
+/* comp[n]: label of each nucleus's node at the last pass (0: not gas); remaining[n]: budgets. */
+int sc_nuclei(struct sc_sim* sim, uint32_t* comp, double* remaining);
+int sc_time(struct sc_sim* sim, int64_t* step);
+
+/* State access for tests and checkpoints.  f is [q][N] FP64 post-streaming populations f_i(x, t)
+ * (velocity order: the lattice order of the library, see sc_lattice); set_equilibrium writes
+ * f = f_eq(rho, u) with u [d][N] or NULL.  Bubble registry and step count are unchanged. */
+int sc_lattice(int32_t lattice, int32_t* e /*[q][3]*/, double* w /*[q]*/);
+int sc_get_populations(struct sc_sim* sim, double* f);
+int sc_set_populations(struct sc_sim* sim, const double* f);
+int sc_set_equilibrium(struct sc_sim* sim, const double* rho, const double* u);
+/* Runs a test pass now, with the merge criterion.  */
+int sc_test_pass(struct sc_sim* sim);
+
+/* Per-kernel-class timing with HIP events on the simulation's stream: enable != 0 starts
+ * recording (and clears the counters); sc_profile_read returns the summed kernel time in ms and
+ * the launch count of one class since then. */
+int sc_profile(struct sc_sim* sim, int32_t enable);
+int sc_profile_read(struct sc_sim* sim, int32_t kernel_class, double* ms, int64_t* launches);
+
+/* Tile shape and compute type chosen for the step kernel (after tuning or from sc_params). */
+int sc_step_config(struct sc_sim* sim, int32_t* tile_x, int32_t* tile_y, int32_t* tile_z);
+int sc_compute_type(struct sc_sim* sim, int32_t* compute);
+
+typedef struct sc_sim sc_sim;
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -3,4 +3,4 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg import this package.
 The product library neither links nor calls it.
 """
-from .oracle import OracleSim, label_mask, feq, lattice, uniform, splitmix64  # noqa: F401
+from .oracle import OracleSim, label_mask, feq, lattice, uniform, splitmix64, num_threads  # noqa: F401

@@ -73,6 +73,8 @@ def _load():
     lib.orc_uniform.argtypes = [C.c_uint64, C.c_uint64]
     lib.orc_splitmix64.restype = C.c_uint64
     lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_num_threads.restype = C.c_int
+    lib.orc_num_threads.argtypes = []
     _lib = lib
     return lib
 
@@ -104,6 +106,10 @@ def uniform(seed, idx):
 
 def splitmix64(seed, k):
     return _load().orc_splitmix64(seed, k)
+
+
+def num_threads():
+    return _load().orc_num_threads()
 
 
 def label_mask(q, shape, mask):

@@ -116,6 +116,7 @@ void orc_lattice(int q, int* e /*[q][3]*/, double* w /*[q]*/);
 void orc_feq(int q, double rho, const double* u /*[3]*/, double* out /*[q]*/);
 double orc_uniform(uint64_t seed, uint64_t idx);  /* U(seed, idx) in [0, 1) */
 uint64_t orc_splitmix64(uint64_t seed, uint64_t k); /* k-th output (k >= 1) of the stream */
+int orc_num_threads(void);                            /* OpenMP threads the oracle uses */
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,1035 @@
+// sc_api.hip -- runtime and C ABI of libsc (see include/sc.h).
+//
+// Host side: parameter validation, device buffers, the time-step loop, and the bubble registry
+// (nuclei, FP64 agent budgets, merge and topological events).  All per-node work runs in the
+// HIP kernels of sc_step.hip and sc_test.hip; the host touches only per-bubble tables.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sc_internal.hpp"
+
+using namespace sc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct ProfRec {
+    hipEvent_t a, b;
+    int cls;
+};
+
+}  // namespace
+
+struct sc_sim {
+    sc_params p;
+    sc_allocator alloc;
+    bool has_alloc = false;
+    int q = 9, d = 2;
+    int64_t N = 0;
+    double theta = 0.0, rho_ref = 0.0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t es = 4;
+    int compute = SC_COMPUTE_F64;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    StepShape shape{};
+    int64_t t = 0;
+    int latched = 0;
+
+    // scratch buffers (allocated on first use)
+    DevBuf parent, labels, labels2, slots, psi, rho_out, u_out, p_out, lap_out, partials, small,
+        tmp64, mask8, nodes, list_node, list_slot, add_tab, pair_buf, res_buf, bub_tab;
+    bool slots_ready = false;
+
+    // nuclei (Sec. 3.1) and agent budgets (Sec. 3)
+    std::vector<double> cen, rad, rem;
+    double rate = 0.0;
+    std::vector<int64_t> nuc_node;
+    std::vector<uint32_t> comp;
+    std::vector<int> merge_parent, topo_parent;
+
+    // last test pass
+    std::vector<sc_bubble> bub;
+    std::vector<std::vector<int>> bub_nuclei;
+    bool have_labels = false;
+    int64_t list_count = 0;
+
+    // source schedule: add_host[s * nb + b] for the steps of the current chunk
+    std::vector<double> add_host;
+    std::vector<double> rem_host;  // rem after each step of the chunk, [s * n + k]
+    std::vector<char> step_active;
+    int chunk_len = 0, chunk_pos = 0;
+
+    std::vector<sc_merge_event> events;
+    std::vector<sc_topo_event> topo;
+
+    bool prof = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+void* dev_alloc(sc_sim* s, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (s->has_alloc) return s->alloc.alloc(bytes, s->alloc.user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void dev_free(sc_sim* s, void* p)
+{
+    if (!p) return;
+    if (s->has_alloc)
+        s->alloc.free(p, s->alloc.user);
+    else
+        (void)hipFree(p);
+}
+
+int device_fail(sc_sim* s, hipError_t e, const char* what)
+{
+    s->latched = SC_E_DEVICE;
+    return fail(SC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPX(call)                                                                               \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return device_fail(s, e_, #call);                                  \
+    } while (0)
+
+int ensure(sc_sim* s, DevBuf& b, size_t bytes)
+{
+    if (b.bytes >= bytes && b.p) return SC_OK;
+    if (b.p) {
+        // the stream may still use the old buffer
+        HIPX(hipStreamSynchronize(s->stream));
+        dev_free(s, b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    b.p = dev_alloc(s, bytes);
+    if (!b.p) return fail(SC_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    b.bytes = bytes;
+    return SC_OK;
+}
+
+#define TRY(expr)                                                                                \
+    do {                                                                                         \
+        int rc_ = (expr);                                                                        \
+        if (rc_ != SC_OK) return rc_;                                                            \
+    } while (0)
+
+int check_usable(sc_sim* s)
+{
+    if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
+    if (s->latched)
+        return fail(SC_E_STATE, "simulation latched by an earlier error (" +
+                                    std::to_string(s->latched) + ")");
+    return SC_OK;
+}
+
+FieldArgs field_args(const sc_sim* s)
+{
+    FieldArgs a;
+    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
+    a.N = s->N;
+    a.G = (float)s->p.G;
+    a.rho_ref = (float)s->rho_ref;
+    a.Gd = s->p.G;
+    a.rho_ref_d = s->rho_ref;
+    a.theta = s->theta;
+    return a;
+}
+
+InitArgs init_args(const sc_sim* s, double rho)
+{
+    InitArgs a;
+    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
+    a.N = s->N;
+    a.rho = rho;
+    a.amp = s->p.noise_amp;
+    a.rho_ref = s->rho_ref;
+    a.seed = s->p.noise_seed;
+    return a;
+}
+
+StepShape default_shape(const sc_params& p)
+{
+    StepShape sh;
+    if (p.lattice == SC_D2Q9) {
+        sh.tile_x = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
+        sh.tile_y = 1;
+        const int64_t tiles = (p.nx + sh.tile_x - 1) / sh.tile_x;
+        int64_t planes = (tiles * p.ny + 2047) / 2048;  // about 2048 blocks
+        sh.tile_z = (int)std::max<int64_t>(4, std::min<int64_t>(64, planes));
+    } else {
+        sh.tile_x = 32;
+        sh.tile_y = 8;
+        sh.tile_z = 16;
+    }
+    return sh;
+}
+
+int prof_begin(sc_sim* s, int cls, hipEvent_t* out_b)
+{
+    *out_b = nullptr;
+    if (!s->prof) return SC_OK;
+    ProfRec r;
+    r.cls = cls;
+    for (hipEvent_t* e : {&r.a, &r.b}) {
+        if (!s->pool.empty()) {
+            *e = s->pool.back();
+            s->pool.pop_back();
+        } else {
+            HIPX(hipEventCreate(e));
+        }
+    }
+    HIPX(hipEventRecord(r.a, s->stream));
+    s->recs.push_back(r);
+    *out_b = r.b;
+    return SC_OK;
+}
+
+int prof_end(sc_sim* s, hipEvent_t b)
+{
+    if (!s->prof || !b) return SC_OK;
+    HIPX(hipEventRecord(b, s->stream));
+    return SC_OK;
+}
+
+// ---- FP64 bookkeeping of the registry (identical arithmetic to the method statement) ---------
+int uf_find(std::vector<int>& parent, int k)
+{
+    while (parent[k] != k) k = parent[k];
+    return k;
+}
+
+double min_image(double d, int n) { return d - n * std::floor(d / n + 0.5); }
+
+int64_t nearest_node(const sc_sim* s, const double* c)
+{
+    auto wrapi = [](int a, int n) {
+        int r = a % n;
+        return r < 0 ? r + n : r;
+    };
+    const int x = wrapi((int)std::floor(c[0] + 0.5), s->p.nx);
+    const int y = wrapi((int)std::floor(c[1] + 0.5), s->p.ny);
+    const int z = (s->d == 3) ? wrapi((int)std::floor(c[2] + 0.5), s->p.nz) : 0;
+    return (int64_t)x + (int64_t)s->p.nx * ((int64_t)y + (int64_t)s->p.ny * z);
+}
+
+// Source schedule for the next `len` steps: bubbles frozen, budgets spent in nucleus order.
+void build_schedule(sc_sim* s, int len)
+{
+#pragma clang fp contract(off)
+    const int nb = (int)s->bub.size();
+    const int n = (int)s->rem.size();
+    s->chunk_len = len;
+    s->chunk_pos = 0;
+    s->add_host.assign((size_t)len * std::max(nb, 1), 0.0);
+    s->rem_host.assign((size_t)len * std::max(n, 1), 0.0);
+    s->step_active.assign((size_t)len, 0);
+    std::vector<double> rem = s->rem;
+    for (int st = 0; st < len; ++st) {
+        if (s->rate > 0.0) {
+            for (int b = 0; b < nb; ++b) {
+                double dm = 0.0;
+                for (int k : s->bub_nuclei[b]) {
+                    const double dk = rem[k] < s->rate ? rem[k] : s->rate;
+                    dm += dk;
+                    rem[k] -= dk;
+                }
+                const double add = dm / (double)s->bub[b].n;
+                s->add_host[(size_t)st * nb + b] = add;
+                if (add != 0.0) s->step_active[st] = 1;
+            }
+        }
+        for (int k = 0; k < n; ++k) s->rem_host[(size_t)st * n + k] = rem[k];
+    }
+}
+
+int upload_schedule(sc_sim* s)
+{
+    const int nb = (int)s->bub.size();
+    if (nb == 0 || s->chunk_len == 0) return SC_OK;
+    const size_t bytes = sizeof(double) * (size_t)s->chunk_len * nb;
+    TRY(ensure(s, s->add_tab, bytes));
+    HIPX(hipMemcpyAsync(s->add_tab.p, s->add_host.data(), bytes, hipMemcpyHostToDevice,
+                        s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int schedule_chunk_len(const sc_sim* s)
+{
+    return s->p.test_every > 0 ? s->p.test_every : 1024;
+}
+
+// ---- test pass (Fig. 1 step 7; Sec. 3.1 eta_m) ------------------------------------------------
+int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uint8_t* mask_host)
+{
+    const FieldArgs fa = field_args(s);
+    TRY(ensure(s, s->parent, sizeof(uint32_t) * (size_t)s->N));
+    TRY(ensure(s, s->small, 4096));
+    if (mask_host) {
+        TRY(ensure(s, s->mask8, (size_t)s->N));
+        HIPX(hipMemcpyAsync(s->mask8.p, mask_host, (size_t)s->N, hipMemcpyHostToDevice,
+                            s->stream));
+        HIPX(launch_mask_from_bytes((const uint8_t*)s->mask8.p, (uint32_t*)s->parent.p, s->N,
+                                    s->stream));
+    } else {
+        HIPX(launch_mask_from_rho(s->q, s->p.storage, s->f[s->cur], (uint32_t*)s->parent.p, fa,
+                                  s->stream));
+    }
+    HIPX(launch_union(s->q, (uint32_t*)s->parent.p, fa, s->stream));
+    uint32_t* ncomp_d = (uint32_t*)((char*)s->small.p + 64);
+    HIPX(launch_fill_i32((int32_t*)ncomp_d, 0, 1, s->stream));
+    HIPX(launch_flatten((uint32_t*)s->parent.p, labels_d, ncomp_d, s->N, s->stream));
+    if (ncomp_host) {
+        HIPX(hipMemcpyAsync(ncomp_host, ncomp_d, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                            s->stream));
+        HIPX(hipStreamSynchronize(s->stream));
+    }
+    return SC_OK;
+}
+
+int totals_now(sc_sim* s, double out[4])
+{
+    const FieldArgs fa = field_args(s);
+    TRY(ensure(s, s->partials, sizeof(double) * 4 * (size_t)totals_blocks(s->N)));
+    TRY(ensure(s, s->small, 4096));
+    double* out_d = (double*)s->small.p;
+    HIPX(launch_totals(s->q, s->p.storage, s->f[s->cur], (double*)s->partials.p, out_d, fa,
+                       s->stream));
+    HIPX(hipMemcpyAsync(out, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int test_pass(sc_sim* s, bool with_criterion)
+{
+#pragma clang fp contract(off)
+    const FieldArgs fa = field_args(s);
+    const int n = (int)s->rad.size();  // nucleus count (cen holds 3 values per nucleus)
+    hipEvent_t pe;
+    TRY(prof_begin(s, SC_KERNEL_TEST, &pe));
+
+    TRY(ensure(s, s->labels, sizeof(uint32_t) * (size_t)s->N));
+    TRY(label_current(s, (uint32_t*)s->labels.p, nullptr, nullptr));
+    s->have_labels = true;
+
+    double tot[4];
+    TRY(totals_now(s, tot));
+    const bool finite = std::isfinite(tot[0]) && std::isfinite(tot[1]) &&
+                        std::isfinite(tot[2]) && std::isfinite(tot[3]);
+
+    // nucleus map: label at each nucleus node
+    s->comp.assign((size_t)n, 0u);
+    if (n > 0) {
+        TRY(ensure(s, s->nodes, sizeof(int64_t) * n + sizeof(uint32_t) * n));
+        int64_t* nodes_d = (int64_t*)s->nodes.p;
+        uint32_t* comp_d = (uint32_t*)((char*)s->nodes.p + sizeof(int64_t) * n);
+        HIPX(hipMemcpyAsync(nodes_d, s->nuc_node.data(), sizeof(int64_t) * n,
+                            hipMemcpyHostToDevice, s->stream));
+        HIPX(launch_gather_labels((const uint32_t*)s->labels.p, nodes_d, comp_d, n, s->N,
+                                  s->stream));
+        HIPX(hipMemcpyAsync(s->comp.data(), comp_d, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
+                            s->stream));
+        HIPX(hipStreamSynchronize(s->stream));
+    }
+
+    // bubbles: distinct nonzero labels held by nuclei, ascending
+    std::vector<uint32_t> distinct;
+    for (int k = 0; k < n; ++k)
+        if (s->comp[k]) distinct.push_back(s->comp[k]);
+    std::sort(distinct.begin(), distinct.end());
+    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+    const int nb = (int)distinct.size();
+    s->bub.assign((size_t)nb, sc_bubble{});
+    s->bub_nuclei.assign((size_t)nb, std::vector<int>());
+    for (int b = 0; b < nb; ++b) {
+        s->bub[b].label = distinct[b];
+        s->bub[b].nucleus = -1;
+    }
+    for (int k = 0; k < n; ++k) {
+        if (!s->comp[k]) continue;
+        const int b = (int)(std::lower_bound(distinct.begin(), distinct.end(), s->comp[k]) -
+                            distinct.begin());
+        if (s->bub[b].nucleus < 0) s->bub[b].nucleus = k;
+        s->bub[b].n_nuclei++;
+        s->bub_nuclei[b].push_back(k);
+    }
+
+    s->list_count = 0;
+    if (nb > 0) {
+        if (!s->slots_ready) {
+            TRY(ensure(s, s->slots, sizeof(int32_t) * (size_t)s->N));
+            HIPX(launch_fill_i32((int32_t*)s->slots.p, -1, s->N, s->stream));
+            s->slots_ready = true;
+        }
+        // per-bubble tables: labels, anchors, counts, offset sums, feed flags
+        const size_t off_anchor = sizeof(uint32_t) * nb;
+        const size_t off_count = ((off_anchor + sizeof(int32_t) * 3 * nb) + 255) & ~size_t(255);
+        const size_t off_sums = off_count + sizeof(unsigned long long) * nb;
+        const size_t off_feed = off_sums + sizeof(unsigned long long) * 3 * nb;
+        const size_t bytes = off_feed + sizeof(int32_t) * nb;
+        TRY(ensure(s, s->bub_tab, bytes));
+        char* base = (char*)s->bub_tab.p;
+        std::vector<int32_t> anchors((size_t)3 * nb);
+        for (int b = 0; b < nb; ++b) {
+            const int64_t a0 = s->nuc_node[s->bub[b].nucleus];
+            anchors[3 * b + 0] = (int32_t)(a0 % s->p.nx);
+            anchors[3 * b + 1] = (int32_t)((a0 / s->p.nx) % s->p.ny);
+            anchors[3 * b + 2] = (int32_t)(a0 / ((int64_t)s->p.nx * s->p.ny));
+        }
+        HIPX(hipMemcpyAsync(base, distinct.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice,
+                            s->stream));
+        HIPX(hipMemcpyAsync(base + off_anchor, anchors.data(), sizeof(int32_t) * 3 * nb,
+                            hipMemcpyHostToDevice, s->stream));
+        HIPX(launch_fill_u64((unsigned long long*)(base + off_count), 0ull, 4 * (int64_t)nb,
+                             s->stream));
+        HIPX(launch_set_slots((int32_t*)s->slots.p, (const uint32_t*)base, nb, 0, s->stream));
+        HIPX(launch_stats((const uint32_t*)s->labels.p, (const int32_t*)s->slots.p,
+                          (const int32_t*)(base + off_anchor), (unsigned long long*)(base + off_count),
+                          (unsigned long long*)(base + off_sums), fa, s->stream));
+        std::vector<unsigned long long> cnt((size_t)nb), sums((size_t)3 * nb);
+        HIPX(hipMemcpyAsync(cnt.data(), base + off_count, sizeof(unsigned long long) * nb,
+                            hipMemcpyDeviceToHost, s->stream));
+        HIPX(hipMemcpyAsync(sums.data(), base + off_sums, sizeof(unsigned long long) * 3 * nb,
+                            hipMemcpyDeviceToHost, s->stream));
+        HIPX(hipStreamSynchronize(s->stream));
+        for (int b = 0; b < nb; ++b) {
+            sc_bubble& B = s->bub[b];
+            B.n = (int64_t)cnt[b];
+            for (int c = 0; c < 3; ++c)
+                B.centroid[c] = (double)anchors[3 * b + c] +
+                                (double)(int64_t)sums[3 * b + c] / (double)B.n;
+            if (s->d == 2) {
+                B.centroid[2] = 0.0;
+                B.radius = std::sqrt((double)B.n / M_PI);
+            } else {
+                B.radius = std::cbrt(3.0 * (double)B.n / (4.0 * M_PI));
+            }
+        }
+
+        // gas-node list of the bubbles the source feeds until the next pass
+        std::vector<int32_t> feed((size_t)nb, 0);
+        int64_t cap = 0;
+        if (s->rate > 0.0) {
+            for (int b = 0; b < nb; ++b) {
+                for (int k : s->bub_nuclei[b])
+                    if (s->rem[k] > 0.0) feed[b] = 1;
+                if (feed[b]) cap += s->bub[b].n;
+            }
+        }
+        if (cap > 0) {
+            HIPX(hipMemcpyAsync(base + off_feed, feed.data(), sizeof(int32_t) * nb,
+                                hipMemcpyHostToDevice, s->stream));
+            TRY(ensure(s, s->list_node, sizeof(uint32_t) * (size_t)cap));
+            TRY(ensure(s, s->list_slot, sizeof(int32_t) * (size_t)cap));
+            TRY(ensure(s, s->small, 4096));
+            unsigned int* cnt_d = (unsigned int*)((char*)s->small.p + 128);
+            HIPX(launch_fill_i32((int32_t*)cnt_d, 0, 1, s->stream));
+            HIPX(launch_gas_list((const uint32_t*)s->labels.p, (const int32_t*)s->slots.p,
+                                 (const int32_t*)(base + off_feed), (uint32_t*)s->list_node.p,
+                                 (int32_t*)s->list_slot.p, cnt_d, s->N, s->stream));
+            unsigned int got = 0;
+            HIPX(hipMemcpyAsync(&got, cnt_d, sizeof(got), hipMemcpyDeviceToHost, s->stream));
+            HIPX(hipStreamSynchronize(s->stream));
+            s->list_count = got;
+        }
+        HIPX(launch_set_slots((int32_t*)s->slots.p, (const uint32_t*)base, nb, 1, s->stream));
+    }
+
+    // topological merges: nuclei of one component join one group (smallest index leads)
+    for (int b = 0; b < nb; ++b) {
+        const int k0 = s->bub[b].nucleus;
+        for (int k : s->bub_nuclei[b]) {
+            if (k == k0) continue;
+            const int ra = uf_find(s->topo_parent, k0), rb = uf_find(s->topo_parent, k);
+            if (ra == rb) continue;
+            sc_topo_event te;
+            te.step = s->t;
+            te.nucleus_a = std::min(ra, rb);
+            te.nucleus_b = std::max(ra, rb);
+            s->topo.push_back(te);
+            s->topo_parent[te.nucleus_b] = te.nucleus_a;
+        }
+    }
+
+    // merge criterion on candidate pairs (pairs in label order, state of the pass start)
+    if (with_criterion && nb >= 2) {
+        std::vector<MergePair> pairs;
+        std::vector<std::pair<int, int>> who;
+        for (int a = 0; a < nb; ++a) {
+            for (int b = a + 1; b < nb; ++b) {
+                const sc_bubble& A = s->bub[a];
+                const sc_bubble& B = s->bub[b];
+                if (uf_find(s->merge_parent, A.nucleus) == uf_find(s->merge_parent, B.nucleus))
+                    continue;
+                double dv[3];
+                dv[0] = min_image(B.centroid[0] - A.centroid[0], s->p.nx);
+                dv[1] = min_image(B.centroid[1] - A.centroid[1], s->p.ny);
+                dv[2] = (s->d == 3) ? min_image(B.centroid[2] - A.centroid[2], s->p.nz) : 0.0;
+                const double dist = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+                if (dist > A.radius + B.radius + (double)s->p.film_max) continue;
+                const int T = (int)std::ceil(dist);
+                if (T <= 0) continue;
+                MergePair mp;
+                for (int c = 0; c < 3; ++c) {
+                    mp.cen_a[c] = A.centroid[c];
+                    mp.dv[c] = dv[c];
+                }
+                mp.label_a = A.label;
+                mp.label_b = B.label;
+                mp.T = T;
+                mp.pad = 0;
+                pairs.push_back(mp);
+                who.emplace_back(a, b);
+            }
+        }
+        const int np = (int)pairs.size();
+        if (np > 0) {
+            TRY(ensure(s, s->pair_buf, sizeof(MergePair) * np));
+            TRY(ensure(s, s->res_buf, sizeof(MergeResult) * np));
+            HIPX(hipMemcpyAsync(s->pair_buf.p, pairs.data(), sizeof(MergePair) * np,
+                                hipMemcpyHostToDevice, s->stream));
+            HIPX(launch_merge(s->q, s->p.storage, s->f[s->cur], (const uint32_t*)s->labels.p,
+                              (const MergePair*)s->pair_buf.p, (MergeResult*)s->res_buf.p, np,
+                              s->p.film_max, fa, s->stream));
+            std::vector<MergeResult> res((size_t)np);
+            HIPX(hipMemcpyAsync(res.data(), s->res_buf.p, sizeof(MergeResult) * np,
+                                hipMemcpyDeviceToHost, s->stream));
+            HIPX(hipStreamSynchronize(s->stream));
+            std::vector<std::pair<int, int>> fired;
+            for (int k = 0; k < np; ++k) {
+                if (!res[k].fired) continue;
+                const sc_bubble& A = s->bub[who[k].first];
+                const sc_bubble& B = s->bub[who[k].second];
+                sc_merge_event e;
+                std::memset(&e, 0, sizeof(e));
+                e.step = s->t;
+                e.nucleus_a = A.nucleus;
+                e.nucleus_b = B.nucleus;
+                e.label_a = A.label;
+                e.label_b = B.label;
+                e.film_node = res[k].film_node;
+                e.film_len = res[k].film_len;
+                e.lap_p = res[k].lap_p;
+                e.rho_film = res[k].rho_film;
+                s->events.push_back(e);
+                fired.emplace_back(A.nucleus, B.nucleus);
+            }
+            // eta_m: 1 -> 0, applied after every pair was tested
+            for (auto& pr : fired) {
+                const int ra = uf_find(s->merge_parent, pr.first);
+                const int rb = uf_find(s->merge_parent, pr.second);
+                if (ra == rb) continue;
+                if (ra < rb) s->merge_parent[rb] = ra; else s->merge_parent[ra] = rb;
+            }
+        }
+    }
+
+    build_schedule(s, schedule_chunk_len(s));
+    TRY(upload_schedule(s));
+    TRY(prof_end(s, pe));
+    if (!finite) {
+        s->latched = SC_E_NUMERIC;
+        return fail(SC_E_NUMERIC, "non-finite FP64 total at step " + std::to_string(s->t));
+    }
+    return SC_OK;
+}
+
+int validate(const sc_params* p)
+{
+    if (!p) return fail(SC_E_INVAL, "NULL parameters");
+    if (p->abi_version != SC_ABI_VERSION) return fail(SC_E_INVAL, "abi_version mismatch");
+    if (p->lattice != SC_D2Q9 && p->lattice != SC_D3Q19) return fail(SC_E_INVAL, "lattice must be 9 or 19");
+    if (p->nx < 4 || p->ny < 4) return fail(SC_E_INVAL, "nx and ny must be >= 4");
+    if (p->lattice == SC_D2Q9 && p->nz != 1) return fail(SC_E_INVAL, "D2Q9 needs nz == 1");
+    if (p->lattice == SC_D3Q19 && p->nz < 4) return fail(SC_E_INVAL, "D3Q19 needs nz >= 4");
+    const double N = (double)p->nx * p->ny * p->nz;
+    if (N > 2147483000.0) return fail(SC_E_INVAL, "box larger than 2^31 nodes");
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(SC_E_INVAL, "tau must be > 0.5");
+    if (!std::isfinite(p->G)) return fail(SC_E_INVAL, "G must be finite");
+    if (!(p->rho_liquid > 0.0) || !std::isfinite(p->rho_liquid)) return fail(SC_E_INVAL, "rho_liquid must be > 0");
+    if (!(p->rho_gas > 0.0) || !std::isfinite(p->rho_gas)) return fail(SC_E_INVAL, "rho_gas must be > 0");
+    if (!(p->noise_amp >= 0.0) || !std::isfinite(p->noise_amp)) return fail(SC_E_INVAL, "noise_amp must be >= 0");
+    if (!std::isfinite(p->gas_threshold)) return fail(SC_E_INVAL, "gas_threshold must be finite");
+    if (p->test_every < 0) return fail(SC_E_INVAL, "test_every must be >= 0");
+    if (p->film_max < 1) return fail(SC_E_INVAL, "film_max must be >= 1");
+    if (p->storage < SC_STORE_F32 || p->storage > SC_STORE_BF16) return fail(SC_E_INVAL, "unknown storage");
+    if (p->compute < SC_COMPUTE_AUTO || p->compute > SC_COMPUTE_F64) return fail(SC_E_INVAL, "unknown compute type");
+    if (p->compute == SC_COMPUTE_F64 && p->storage != SC_STORE_F32)
+        return fail(SC_E_UNSUPPORTED, "FP64 arithmetic is offered on FP32 storage only");
+    if (!std::isfinite(p->rho_ref)) return fail(SC_E_INVAL, "rho_ref must be finite");
+    if (p->allocator && (!p->allocator->alloc || !p->allocator->free))
+        return fail(SC_E_INVAL, "allocator needs alloc and free");
+    if (p->tile_x || p->tile_y || p->tile_z) {
+        StepShape sh{p->tile_x, p->lattice == SC_D2Q9 ? 1 : p->tile_y, p->tile_z};
+        if (!step_shape_supported(p->lattice, sh)) return fail(SC_E_INVAL, "unsupported step tile");
+    }
+    return SC_OK;
+}
+
+void release(sc_sim* s)
+{
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (DevBuf* b : {&s->parent, &s->labels, &s->labels2, &s->slots, &s->psi, &s->rho_out,
+                      &s->u_out, &s->p_out, &s->lap_out, &s->partials, &s->small, &s->tmp64,
+                      &s->mask8, &s->nodes, &s->list_node, &s->list_slot, &s->add_tab,
+                      &s->pair_buf, &s->res_buf, &s->bub_tab})
+        dev_free(s, b->p);
+    dev_free(s, s->f[0]);
+    dev_free(s, s->f[1]);
+    for (auto& r : s->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : s->pool) (void)hipEventDestroy(e);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+}  // namespace
+
+// ==============================================================================================
+// C ABI
+// ==============================================================================================
+extern "C" {
+
+uint32_t sc_abi_version(void) { return SC_ABI_VERSION; }
+
+const char* sc_last_error(void) { return g_err.c_str(); }
+
+int sc_params_init(sc_params* p)
+{
+    if (!p) return fail(SC_E_INVAL, "NULL parameters");
+    std::memset(p, 0, sizeof(*p));
+    p->abi_version = SC_ABI_VERSION;
+    p->lattice = SC_D2Q9;
+    p->nx = 128; p->ny = 128; p->nz = 1;
+    p->tau = 1.0; p->G = -5.0;
+    p->rho_liquid = 1.93; p->rho_gas = 0.16;
+    p->noise_amp = 1e-3; p->noise_seed = 1;
+    p->gas_threshold = 0.0;
+    p->test_every = 10;
+    p->film_max = 8;
+    p->storage = SC_STORE_F32;
+    p->rho_ref = -1.0;
+    return SC_OK;
+}
+
+int sc_create(const sc_params* p, sc_sim** out)
+{
+    if (!out) return fail(SC_E_INVAL, "NULL output handle");
+    TRY(validate(p));
+    sc_sim* s = new sc_sim();
+    s->p = *p;
+    if (p->allocator) {
+        s->alloc = *p->allocator;
+        s->has_alloc = true;
+    }
+    s->q = p->lattice;
+    s->d = p->lattice == SC_D2Q9 ? 2 : 3;
+    s->N = (int64_t)p->nx * p->ny * p->nz;
+    s->theta = p->gas_threshold > 0.0 ? p->gas_threshold : 0.5 * (p->rho_liquid + p->rho_gas);
+    s->rho_ref = p->rho_ref >= 0.0 ? p->rho_ref : (p->storage == SC_STORE_F32 ? 0.0 : p->rho_liquid);
+    s->es = storage_bytes(p->storage);
+    s->compute = p->compute != SC_COMPUTE_AUTO
+                     ? p->compute
+                     : (p->storage == SC_STORE_F32 ? SC_COMPUTE_F64 : SC_COMPUTE_F32);
+    if (p->tile_x || p->tile_y || p->tile_z)
+        s->shape = StepShape{p->tile_x, p->lattice == SC_D2Q9 ? 1 : p->tile_y, p->tile_z};
+    else
+        s->shape = default_shape(*p);
+    if (p->stream) {
+        s->stream = (hipStream_t)p->stream;
+    } else {
+        if (hipStreamCreate(&s->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return fail(SC_E_DEVICE, "hipStreamCreate failed");
+        }
+        s->own_stream = true;
+    }
+    const size_t bytes = (size_t)s->q * (size_t)s->N * s->es;
+    s->f[0] = dev_alloc(s, bytes);
+    s->f[1] = dev_alloc(s, bytes);
+    if (!s->f[0] || !s->f[1]) {
+        release(s);
+        delete s;
+        return fail(SC_E_NOMEM, "population buffers (" + std::to_string(2 * bytes) + " bytes)");
+    }
+    hipError_t e = launch_init(s->q, p->storage, s->f[0], init_args(s, p->rho_liquid), s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        std::string m = std::string("initial fill: ") + hipGetErrorString(e);
+        release(s);
+        delete s;
+        return fail(SC_E_DEVICE, m);
+    }
+    *out = s;
+    return SC_OK;
+}
+
+int sc_destroy(sc_sim* s)
+{
+    if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
+    release(s);
+    delete s;
+    return SC_OK;
+}
+
+int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* radius,
+                   const double* budget, double rate)
+{
+    TRY(check_usable(s));
+    if (n < 0) return fail(SC_E_INVAL, "n must be >= 0");
+    if (n > 0 && (!centre || !radius || !budget)) return fail(SC_E_INVAL, "NULL nucleus arrays");
+    if (!(rate >= 0.0) || !std::isfinite(rate)) return fail(SC_E_INVAL, "rate must be finite and >= 0");
+    for (int k = 0; k < n; ++k) {
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(centre[3 * k + c])) return fail(SC_E_INVAL, "non-finite centre");
+        if (!std::isfinite(radius[k])) return fail(SC_E_INVAL, "non-finite radius");
+        if (!(budget[k] >= 0.0) || !std::isfinite(budget[k])) return fail(SC_E_INVAL, "budget must be finite and >= 0");
+    }
+    s->cen.assign((size_t)3 * n, 0.0);
+    s->rad.assign((size_t)n, 0.0);
+    s->rem.assign((size_t)n, 0.0);
+    s->nuc_node.assign((size_t)n, 0);
+    s->merge_parent.resize((size_t)n);
+    s->topo_parent.resize((size_t)n);
+    s->rate = rate;
+    for (int k = 0; k < n; ++k) {
+        for (int c = 0; c < 3; ++c) s->cen[3 * k + c] = centre[3 * k + c];
+        if (s->d == 2) s->cen[3 * k + 2] = 0.0;
+        s->rad[k] = radius[k];
+        s->rem[k] = budget[k];
+        s->nuc_node[k] = nearest_node(s, &s->cen[3 * k]);
+        s->merge_parent[k] = k;
+        s->topo_parent[k] = k;
+    }
+    const InitArgs ia = init_args(s, s->p.rho_gas);
+    for (int k = 0; k < n; ++k) {
+        if (s->rad[k] < 0.0) continue;
+        HIPX(launch_paint(s->q, s->p.storage, s->f[s->cur], ia, &s->cen[3 * k], s->rad[k],
+                          s->stream));
+    }
+    return test_pass(s, false);
+}
+
+int sc_step(sc_sim* s, int32_t nsteps)
+{
+    TRY(check_usable(s));
+    if (nsteps < 0) return fail(SC_E_INVAL, "nsteps must be >= 0");
+    StepArgs a;
+    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
+    a.planes = s->shape.tile_z;
+    a.N = s->N;
+    a.tau = (float)s->p.tau;
+    a.omega = (float)(1.0 / s->p.tau);
+    a.G = (float)s->p.G;
+    a.rho_ref = (float)s->rho_ref;
+    a.taud = s->p.tau;
+    a.omegad = 1.0 / s->p.tau;
+    a.Gd = s->p.G;
+    a.rho_refd = s->rho_ref;
+    const FieldArgs fa = field_args(s);
+    const int K = s->p.test_every;
+    for (int it = 0; it < nsteps; ++it) {
+        hipEvent_t pe;
+        TRY(prof_begin(s, SC_KERNEL_STEP, &pe));
+        HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a,
+                         s->shape, s->stream));
+        TRY(prof_end(s, pe));
+        s->cur ^= 1;
+        // blowing-agent source after streaming
+        if (s->chunk_pos >= s->chunk_len) {
+            build_schedule(s, schedule_chunk_len(s));
+            TRY(upload_schedule(s));
+        }
+        const int nb = (int)s->bub.size();
+        if (s->step_active.size() && s->step_active[s->chunk_pos] && s->list_count > 0) {
+            TRY(prof_begin(s, SC_KERNEL_SOURCE, &pe));
+            HIPX(launch_source(s->q, s->p.storage, s->f[s->cur], (const uint32_t*)s->list_node.p,
+                               (const int32_t*)s->list_slot.p, s->list_count,
+                               (const double*)s->add_tab.p + (size_t)s->chunk_pos * nb, fa,
+                               s->stream));
+            TRY(prof_end(s, pe));
+        }
+        if (!s->rem.empty() && s->chunk_len > 0) {
+            const size_t n = s->rem.size();
+            std::copy(s->rem_host.begin() + s->chunk_pos * n,
+                      s->rem_host.begin() + (s->chunk_pos + 1) * n, s->rem.begin());
+        }
+        s->chunk_pos++;
+        s->t += 1;
+        if (K > 0 && s->t % K == 0) TRY(test_pass(s, true));
+    }
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_fields(sc_sim* s, float* rho, float* u, double* totals)
+{
+    TRY(check_usable(s));
+    const FieldArgs fa = field_args(s);
+    if (rho || u) {
+        TRY(ensure(s, s->psi, sizeof(double) * (size_t)s->N));
+        if (rho) TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
+        if (u) TRY(ensure(s, s->u_out, sizeof(float) * (size_t)s->N * s->d));
+        HIPX(launch_psi(s->q, s->p.storage, s->f[s->cur], (double*)s->psi.p, fa, s->stream));
+        HIPX(launch_fields(s->q, s->p.storage, s->f[s->cur], (const double*)s->psi.p,
+                           rho ? (float*)s->rho_out.p : nullptr, u ? (float*)s->u_out.p : nullptr,
+                           fa, s->stream));
+        if (rho)
+            HIPX(hipMemcpyAsync(rho, s->rho_out.p, sizeof(float) * (size_t)s->N,
+                                hipMemcpyDeviceToHost, s->stream));
+        if (u)
+            HIPX(hipMemcpyAsync(u, s->u_out.p, sizeof(float) * (size_t)s->N * s->d,
+                                hipMemcpyDeviceToHost, s->stream));
+        HIPX(hipStreamSynchronize(s->stream));
+    }
+    if (totals) TRY(totals_now(s, totals));
+    return SC_OK;
+}
+
+int sc_laplacian_p(sc_sim* s, double* p, double* lap)
+{
+    TRY(check_usable(s));
+    if (!p && !lap) return SC_OK;
+    const FieldArgs fa = field_args(s);
+    TRY(ensure(s, s->p_out, sizeof(double) * (size_t)s->N));
+    HIPX(launch_pressure(s->q, s->p.storage, s->f[s->cur], (double*)s->p_out.p, fa, s->stream));
+    if (lap) {
+        TRY(ensure(s, s->lap_out, sizeof(double) * (size_t)s->N));
+        HIPX(launch_laplacian(s->q, (const double*)s->p_out.p, (double*)s->lap_out.p, fa,
+                              s->stream));
+        HIPX(hipMemcpyAsync(lap, s->lap_out.p, sizeof(double) * (size_t)s->N,
+                            hipMemcpyDeviceToHost, s->stream));
+    }
+    if (p)
+        HIPX(hipMemcpyAsync(p, s->p_out.p, sizeof(double) * (size_t)s->N, hipMemcpyDeviceToHost,
+                            s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_label_bubbles(sc_sim* s, const uint8_t* mask, uint32_t* labels, int64_t* ncomp)
+{
+    TRY(check_usable(s));
+    TRY(ensure(s, s->labels2, sizeof(uint32_t) * (size_t)s->N));
+    uint32_t nc = 0;
+    TRY(label_current(s, (uint32_t*)s->labels2.p, &nc, mask));
+    if (labels)
+        HIPX(hipMemcpyAsync(labels, s->labels2.p, sizeof(uint32_t) * (size_t)s->N,
+                            hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    if (ncomp) *ncomp = nc;
+    return SC_OK;
+}
+
+int sc_merge_events(sc_sim* s, sc_merge_event* out, int32_t cap, int32_t* n_total)
+{
+    if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
+    if (cap < 0 || (cap > 0 && !out)) return fail(SC_E_INVAL, "bad output buffer");
+    const int n = (int)s->events.size();
+    for (int k = 0; k < n && k < cap; ++k) out[k] = s->events[k];
+    if (n_total) *n_total = n;
+    return SC_OK;
+}
+
+int sc_topo_events(sc_sim* s, sc_topo_event* out, int32_t cap, int32_t* n_total)
+{
+    if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
+    if (cap < 0 || (cap > 0 && !out)) return fail(SC_E_INVAL, "bad output buffer");
+    const int n = (int)s->topo.size();
+    for (int k = 0; k < n && k < cap; ++k) out[k] = s->topo[k];
+    if (n_total) *n_total = n;
+    return SC_OK;
+}
+
+int sc_bubbles(sc_sim* s, sc_bubble* out, int32_t cap, int32_t* n_total)
+{
+    if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
+    if (cap < 0 || (cap > 0 && !out)) return fail(SC_E_INVAL, "bad output buffer");
+    const int n = (int)s->bub.size();
+    for (int k = 0; k < n && k < cap; ++k) out[k] = s->bub[k];
+    if (n_total) *n_total = n;
+    return SC_OK;
+}
+
+int sc_last_labels(sc_sim* s, uint32_t* labels)
+{
+    TRY(check_usable(s));
+    if (!labels) return fail(SC_E_INVAL, "NULL labels");
+    if (!s->have_labels) return fail(SC_E_STATE, "no test pass has run yet");
+    HIPX(hipMemcpyAsync(labels, s->labels.p, sizeof(uint32_t) * (size_t)s->N,
+                        hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_nuclei(sc_sim* s, uint32_t* comp, double* remaining)
+{
+    if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
+    for (size_t k = 0; k < s->rem.size(); ++k) {
+        if (comp) comp[k] = k < s->comp.size() ? s->comp[k] : 0u;
+        if (remaining) remaining[k] = s->rem[k];
+    }
+    return SC_OK;
+}
+
+int sc_time(sc_sim* s, int64_t* step)
+{
+    if (!s || !step) return fail(SC_E_INVAL, "NULL argument");
+    *step = s->t;
+    return SC_OK;
+}
+
+int sc_lattice(int32_t lattice, int32_t* e, double* w)
+{
+    static const int e9[9][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                 {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+    static const int e19[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                   {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                   {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                   {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    if (lattice != SC_D2Q9 && lattice != SC_D3Q19) return fail(SC_E_INVAL, "lattice must be 9 or 19");
+    const int q = lattice;
+    for (int i = 0; i < q; ++i) {
+        const int* v = q == 9 ? e9[i] : e19[i];
+        const int m = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        if (e)
+            for (int c = 0; c < 3; ++c) e[3 * i + c] = v[c];
+        if (w) {
+            if (q == 9) w[i] = m == 0 ? 4.0 / 9.0 : (m == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+            else w[i] = m == 0 ? 1.0 / 3.0 : (m == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        }
+    }
+    return SC_OK;
+}
+
+int sc_get_populations(sc_sim* s, double* f)
+{
+    TRY(check_usable(s));
+    if (!f) return fail(SC_E_INVAL, "NULL output");
+    const size_t bytes = sizeof(double) * (size_t)s->q * (size_t)s->N;
+    TRY(ensure(s, s->tmp64, bytes));
+    HIPX(launch_get_f(s->q, s->p.storage, s->f[s->cur], (double*)s->tmp64.p, init_args(s, 0.0),
+                      s->stream));
+    HIPX(hipMemcpyAsync(f, s->tmp64.p, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_set_populations(sc_sim* s, const double* f)
+{
+    TRY(check_usable(s));
+    if (!f) return fail(SC_E_INVAL, "NULL input");
+    const size_t bytes = sizeof(double) * (size_t)s->q * (size_t)s->N;
+    TRY(ensure(s, s->tmp64, bytes));
+    HIPX(hipMemcpyAsync(s->tmp64.p, f, bytes, hipMemcpyHostToDevice, s->stream));
+    HIPX(launch_set_f(s->q, s->p.storage, s->f[s->cur], (const double*)s->tmp64.p,
+                      init_args(s, 0.0), s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_set_equilibrium(sc_sim* s, const double* rho, const double* u)
+{
+    TRY(check_usable(s));
+    if (!rho) return fail(SC_E_INVAL, "NULL rho");
+    for (int64_t n = 0; n < s->N; ++n)
+        if (!(rho[n] > 0.0) || !std::isfinite(rho[n])) return fail(SC_E_INVAL, "rho must be finite and > 0");
+    const size_t nb_rho = sizeof(double) * (size_t)s->N;
+    const size_t bytes = nb_rho * (1 + (u ? s->d : 0));
+    TRY(ensure(s, s->tmp64, bytes));
+    HIPX(hipMemcpyAsync(s->tmp64.p, rho, nb_rho, hipMemcpyHostToDevice, s->stream));
+    if (u)
+        HIPX(hipMemcpyAsync((char*)s->tmp64.p + nb_rho, u, nb_rho * s->d, hipMemcpyHostToDevice,
+                            s->stream));
+    HIPX(launch_set_eq(s->q, s->p.storage, s->f[s->cur], init_args(s, 0.0),
+                       (const double*)s->tmp64.p,
+                       u ? (const double*)((char*)s->tmp64.p + nb_rho) : nullptr, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_test_pass(sc_sim* s)
+{
+    TRY(check_usable(s));
+    return test_pass(s, true);
+}
+
+int sc_profile(sc_sim* s, int32_t enable)
+{
+    TRY(check_usable(s));
+    HIPX(hipStreamSynchronize(s->stream));
+    for (auto& r : s->recs) {
+        s->pool.push_back(r.a);
+        s->pool.push_back(r.b);
+    }
+    s->recs.clear();
+    s->prof = enable != 0;
+    return SC_OK;
+}
+
+int sc_profile_read(sc_sim* s, int32_t cls, double* ms, int64_t* launches)
+{
+    TRY(check_usable(s));
+    HIPX(hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto& r : s->recs) {
+        if (r.cls != cls) continue;
+        float e = 0.0f;
+        HIPX(hipEventElapsedTime(&e, r.a, r.b));
+        tot += e;
+        ++cnt;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = cnt;
+    return SC_OK;
+}
+
+int sc_compute_type(sc_sim* s, int32_t* compute)
+{
+    if (!s || !compute) return fail(SC_E_INVAL, "NULL argument");
+    *compute = s->compute;
+    return SC_OK;
+}
+
+int sc_step_config(sc_sim* s, int32_t* tx, int32_t* ty, int32_t* tz)
+{
+    if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
+    if (tx) *tx = s->shape.tile_x;
+    if (ty) *ty = s->shape.tile_y;
+    if (tz) *tz = s->shape.tile_z;
+    return SC_OK;
+}
+
+}  // extern "C"

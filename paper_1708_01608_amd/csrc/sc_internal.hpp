@@ -1,0 +1,122 @@
+// sc_internal.hpp -- host-side declarations shared by the translation units of libsc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sc.h"
+
+namespace sc {
+
+// Arguments of the fused step kernel.
+struct StepArgs {
+    int nx, ny, nz;
+    int planes;        // planes (z in 3D, rows y in 2D) marched by one block
+    int64_t N;
+    float tau, omega, G, rho_ref;
+    double taud, omegad, Gd, rho_refd;
+};
+
+struct StepShape {
+    int tile_x, tile_y, tile_z;  // tile_y is 1 in 2D; tile_z = planes per block
+};
+
+// storage codes as in sc.h: 0 F32, 1 F16, 2 BF16
+size_t storage_bytes(int storage);
+
+// --- step kernels (sc_step.hip) ------------------------------------------------------------
+bool step_shape_supported(int q, const StepShape& s);
+bool step_combo_supported(int storage, int compute);
+hipError_t launch_step(int q, int storage, int compute, const void* src, void* dst,
+                       const StepArgs& a, const StepShape& s, hipStream_t st);
+
+// --- state kernels (sc_step.hip) -----------------------------------------------------------
+struct InitArgs {
+    int nx, ny, nz;
+    int64_t N;
+    double rho, amp, rho_ref;
+    uint64_t seed;
+};
+hipError_t launch_init(int q, int storage, void* f, const InitArgs& a, hipStream_t st);
+// Paint a ball of radius R around c (minimal image), rho = rho_gas + amp (2U - 1), u = 0.
+hipError_t launch_paint(int q, int storage, void* f, const InitArgs& a, const double c[3],
+                        double R, hipStream_t st);
+hipError_t launch_set_eq(int q, int storage, void* f, const InitArgs& a, const double* rho_d,
+                         const double* u_d, hipStream_t st);
+hipError_t launch_get_f(int q, int storage, const void* f, double* out_d, const InitArgs& a,
+                        hipStream_t st);
+hipError_t launch_set_f(int q, int storage, void* f, const double* in_d, const InitArgs& a,
+                        hipStream_t st);
+
+// --- field / test kernels (sc_test.hip) ----------------------------------------------------
+struct FieldArgs {
+    int nx, ny, nz;
+    int64_t N;
+    float G;
+    float rho_ref;
+    double Gd, rho_ref_d, theta;
+};
+hipError_t launch_psi(int q, int storage, const void* f, double* psi, const FieldArgs& a,
+                      hipStream_t st);
+hipError_t launch_fields(int q, int storage, const void* f, const double* psi, float* rho,
+                         float* u, const FieldArgs& a, hipStream_t st);
+hipError_t launch_pressure(int q, int storage, const void* f, double* p, const FieldArgs& a,
+                           hipStream_t st);
+hipError_t launch_laplacian(int q, const double* p, double* lap, const FieldArgs& a,
+                            hipStream_t st);
+// FP64 totals (M, Jx, Jy, Jz) into out_d[4] (device); partials holds >= totals_blocks() * 4.
+int totals_blocks(int64_t N);
+hipError_t launch_totals(int q, int storage, const void* f, double* partials, double* out_d,
+                         const FieldArgs& a, hipStream_t st);
+
+// Labelling: parent[N] (uint32, 0xffffffff = liquid), labels[N] (1 + root, 0 = liquid).
+hipError_t launch_mask_from_rho(int q, int storage, const void* f, uint32_t* parent,
+                                const FieldArgs& a, hipStream_t st);
+hipError_t launch_mask_from_bytes(const uint8_t* mask_d, uint32_t* parent, int64_t N,
+                                  hipStream_t st);
+hipError_t launch_union(int q, uint32_t* parent, const FieldArgs& a, hipStream_t st);
+hipError_t launch_flatten(uint32_t* parent, uint32_t* labels, uint32_t* ncomp_d, int64_t N,
+                          hipStream_t st);
+
+// Bubble statistics and the merge test.
+hipError_t launch_gather_labels(const uint32_t* labels, const int64_t* nodes_d, uint32_t* out_d,
+                                int n, int64_t N, hipStream_t st);
+hipError_t launch_set_slots(int32_t* slot_of_root, const uint32_t* labels_of_bubbles_d, int nb,
+                            int clear, hipStream_t st);
+hipError_t launch_stats(const uint32_t* labels, const int32_t* slot_of_root,
+                        const int32_t* anchors_d /*[nb][3]*/, unsigned long long* count_d,
+                        unsigned long long* sums_d /*[nb][3]*/, const FieldArgs& a,
+                        hipStream_t st);
+hipError_t launch_gas_list(const uint32_t* labels, const int32_t* slot_of_root,
+                           const int32_t* feed_d /*[nb]: 1 if the bubble is fed*/,
+                           uint32_t* list_node, int32_t* list_slot, unsigned int* count_d,
+                           int64_t N, hipStream_t st);
+
+struct MergePair {
+    double cen_a[3];
+    double dv[3];
+    uint32_t label_a, label_b;
+    int32_t T;
+    int32_t pad;
+};
+struct MergeResult {
+    int32_t fired;
+    int32_t film_len;
+    int64_t film_node;
+    double lap_p;
+    double rho_film;
+};
+hipError_t launch_merge(int q, int storage, const void* f, const uint32_t* labels,
+                        const MergePair* pairs_d, MergeResult* res_d, int npairs, int film_max,
+                        const FieldArgs& a, hipStream_t st);
+
+// Blowing-agent source for one step: f_i(x) += w_i * add[slot] on the listed gas nodes.
+hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
+                         const int32_t* list_slot, int64_t count, const double* add_d,
+                         const FieldArgs& a, hipStream_t st);
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n,
+                           hipStream_t st);
+
+}  // namespace sc

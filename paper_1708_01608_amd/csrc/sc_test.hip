@@ -1,0 +1,636 @@
+// sc_test.hip -- output fields, FP64 EOS / Laplacian / totals, gas labelling, bubble statistics,
+// merge criterion and blowing-agent source of libsc (gfx950).
+//
+// Every kernel reads the pull-layout populations: f_i(x, t) = stored_i(x - e_i) + w_i rho_ref.
+#include "sc_device.hpp"
+#include "sc_internal.hpp"
+
+namespace sc {
+
+static dim3 grid_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+__device__ __forceinline__ void coords3(int64_t n, int nx, int ny, int& x, int& y, int& z)
+{
+    x = (int)(n % nx);
+    const int64_t r = n / nx;
+    y = (int)(r % ny);
+    z = (int)(r / ny);
+}
+
+__device__ __forceinline__ int64_t idx3(int x, int y, int z, int nx, int ny)
+{
+    return (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
+}
+
+// Node x + s * e_i (s = +1 downstream, -1 upstream), periodic.
+template <int Q>
+__device__ __forceinline__ int64_t shifted(int x, int y, int z, int i, int s, const FieldArgs& a)
+{
+    using L = lat<Q>;
+    return idx3(wrap_once(x + s * L::ex[i], a.nx), wrap_once(y + s * L::ey[i], a.ny),
+                wrap_once(z + s * L::ez[i], a.nz), a.nx, a.ny);
+}
+
+// FP32 deviation sum of node n (the same order as the step kernel).
+template <int Q, typename S>
+__device__ __forceinline__ float dev_sum_f(const S* f, int64_t n, const FieldArgs& a, float* g)
+{
+    int x, y, z;
+    coords3(n, a.nx, a.ny, x, y, z);
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        g[i] = load_f(f[(int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a)]);
+        s += g[i];
+    }
+    return s;
+}
+
+// FP64 density of node n: rho_ref + sum of the stored deviations, summed in double.
+template <int Q, typename S>
+__device__ __forceinline__ double rho_d(const S* f, int64_t n, const FieldArgs& a)
+{
+    int x, y, z;
+    coords3(n, a.nx, a.ny, x, y, z);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        s += (double)load_f(f[(int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a)]);
+    return a.rho_ref_d + s;
+}
+
+// ---- psi and the reported fields (FP64 arithmetic, FP32 output) -------------------------------
+template <int Q, typename S>
+__global__ void k_psi(const S* f, double* psi, FieldArgs a)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x)
+        psi[n] = psi_f(rho_d<Q, S>(f, n, a));
+}
+
+// rho and u = (j + F/2)/rho with the Shan-Chen force of the current state.
+template <int Q, typename S>
+__global__ void k_fields(const S* f, const double* psi, float* rho_out, float* u_out, FieldArgs a)
+{
+    using L = lat<Q>;
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+        double g[Q];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            g[i] = (double)load_f(f[(int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a)]);
+            s += g[i];
+        }
+        const double rho = a.rho_ref_d + s;
+        if (rho_out) rho_out[n] = (float)rho;
+        if (!u_out) continue;
+        double j[3] = {0.0, 0.0, 0.0}, F[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            j[0] += g[i] * L::ex[i];
+            j[1] += g[i] * L::ey[i];
+            j[2] += g[i] * L::ez[i];
+        }
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const double pn = psi[shifted<Q>(x, y, z, i, +1, a)];
+            F[0] += L::wd[i] * pn * L::ex[i];
+            F[1] += L::wd[i] * pn * L::ey[i];
+            F[2] += L::wd[i] * pn * L::ez[i];
+        }
+        const double pc = psi[n];
+        for (int c = 0; c < L::d; ++c) {
+            const double Fc = -a.Gd * pc * F[c];
+            u_out[(int64_t)c * a.N + n] = (float)((j[c] + 0.5 * Fc) / rho);
+        }
+    }
+}
+
+// ---- FP64 EOS and its lattice Laplacian (Sec. 3.1, the criterion's operator) ----------------
+template <int Q, typename S>
+__global__ void k_pressure(const S* f, double* p, FieldArgs a)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x)
+        p[n] = pressure_d(rho_d<Q, S>(f, n, a), a.Gd);
+}
+
+template <int Q>
+__global__ void k_laplacian(const double* p, double* lap, FieldArgs a)
+{
+    using L = lat<Q>;
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+        const double pc = p[n];
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) acc += L::wd[i] * (p[shifted<Q>(x, y, z, i, +1, a)] - pc);
+        lap[n] = 6.0 * acc;
+    }
+}
+
+// ---- FP64 totals: wave64 shuffles -> LDS -> one partial per block -> fixed-order final sum ---
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+constexpr int kTotBlocks = 1024;
+
+int totals_blocks(int64_t N)
+{
+    int64_t b = (N + 255) / 256;
+    return (int)(b < kTotBlocks ? (b < 1 ? 1 : b) : kTotBlocks);
+}
+
+// Sums the stored values directly (a permutation of the pulled ones): M = N rho_ref + sum g,
+// J = sum_i e_i sum_y g_i(y).
+template <int Q, typename S>
+__global__ void __launch_bounds__(256) k_totals(const S* f, double* partials, FieldArgs a)
+{
+    using L = lat<Q>;
+    double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double g = (double)load_f(f[(int64_t)i * a.N + n]);
+            m += g;
+            jx += g * L::ex[i];
+            jy += g * L::ey[i];
+            jz += g * L::ez[i];
+        }
+    }
+    __shared__ double red[4][4];
+    m = wave_sum(m); jx = wave_sum(jx); jy = wave_sum(jy); jz = wave_sum(jz);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { red[w][0] = m; red[w][1] = jx; red[w][2] = jy; red[w][3] = jz; }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int k = 0; k < 4; ++k) s += red[k][threadIdx.x];
+        partials[(int64_t)blockIdx.x * 4 + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_totals_final(const double* partials, int nb, double* out, double base_mass)
+{
+    // one thread per component, blocks summed in index order
+    const int c = threadIdx.x;
+    if (c >= 4) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partials[(int64_t)b * 4 + c];
+    out[c] = (c == 0) ? base_mass + s : s;
+}
+
+// ---- gas labelling: lock-free union-find, roots linked towards the smaller index ------------
+constexpr uint32_t kLiquid = 0xffffffffu;
+
+template <int Q, typename S>
+__global__ void k_mask_rho(const S* f, uint32_t* parent, FieldArgs a)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x)
+        parent[n] = (rho_d<Q, S>(f, n, a) < a.theta) ? (uint32_t)n : kLiquid;
+}
+
+__global__ void k_mask_bytes(const uint8_t* mask, uint32_t* parent, int64_t N)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * blockDim.x)
+        parent[n] = mask[n] ? (uint32_t)n : kLiquid;
+}
+
+__device__ __forceinline__ uint32_t load_parent(const uint32_t* parent, uint32_t x)
+{
+    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t find_root(const uint32_t* parent, uint32_t x)
+{
+    uint32_t p = load_parent(parent, x);
+    while (p != x) {
+        x = p;
+        p = load_parent(parent, x);
+    }
+    return x;
+}
+
+// parent values only decrease and always point inside the same set, so a stale read is still an
+// ancestor; atomicMin links root b under a and reports a concurrent re-link through its result.
+__device__ void unite(uint32_t* parent, uint32_t a, uint32_t b)
+{
+    while (true) {
+        a = find_root(parent, a);
+        b = find_root(parent, b);
+        if (a == b) return;
+        if (a > b) { const uint32_t t = a; a = b; b = t; }
+        const uint32_t old = atomicMin(parent + b, a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+template <int Q>
+__global__ void k_union(uint32_t* parent, FieldArgs a)
+{
+    using L = lat<Q>;
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        if (load_parent(parent, (uint32_t)n) == kLiquid) continue;
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+#pragma unroll
+        for (int h = 0; h < L::nhalf; ++h) {
+            const int64_t m = shifted<Q>(x, y, z, L::half[h], +1, a);
+            if (m == n) continue;
+            if (load_parent(parent, (uint32_t)m) == kLiquid) continue;
+            unite(parent, (uint32_t)n, (uint32_t)m);
+        }
+    }
+}
+
+__global__ void k_flatten(const uint32_t* parent, uint32_t* labels, uint32_t* ncomp, int64_t N)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = parent[n];
+        if (p == kLiquid) {
+            labels[n] = 0;
+            continue;
+        }
+        uint32_t r = (uint32_t)n, q = p;
+        while (q != r) {
+            r = q;
+            q = parent[r];
+        }
+        labels[n] = r + 1;
+        if (r == (uint32_t)n) atomicAdd(ncomp, 1u);
+    }
+}
+
+// ---- bubble statistics ------------------------------------------------------------------------
+__global__ void k_gather(const uint32_t* labels, const int64_t* nodes, uint32_t* out, int n,
+                         int64_t N)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t nd = nodes[k];
+    out[k] = (nd >= 0 && nd < N) ? labels[nd] : 0u;
+}
+
+__global__ void k_set_slots(int32_t* slot_of_root, const uint32_t* labs, int nb, int clear)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) slot_of_root[labs[b] - 1] = clear ? -1 : b;
+}
+
+__device__ __forceinline__ int64_t min_image_i(int64_t d, int n)
+{
+    const int64_t h = n / 2;
+    int64_t r = (d + h) % n;
+    if (r < 0) r += n;
+    return r - h;
+}
+
+__global__ void k_stats(const uint32_t* labels, const int32_t* slot_of_root, const int32_t* anchors,
+                        unsigned long long* count, unsigned long long* sums, FieldArgs a)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t L = labels[n];
+        if (!L) continue;
+        const int b = slot_of_root[L - 1];
+        if (b < 0) continue;
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+        const int64_t ox = min_image_i((int64_t)x - anchors[3 * b + 0], a.nx);
+        const int64_t oy = min_image_i((int64_t)y - anchors[3 * b + 1], a.ny);
+        const int64_t oz = min_image_i((int64_t)z - anchors[3 * b + 2], a.nz);
+        atomicAdd(count + b, 1ull);
+        // two's-complement wrap-around makes unsigned adds exact signed sums
+        atomicAdd(sums + 3 * b + 0, (unsigned long long)ox);
+        atomicAdd(sums + 3 * b + 1, (unsigned long long)oy);
+        atomicAdd(sums + 3 * b + 2, (unsigned long long)oz);
+    }
+}
+
+__global__ void k_gas_list(const uint32_t* labels, const int32_t* slot_of_root, const int32_t* feed,
+                           uint32_t* list_node, int32_t* list_slot, unsigned int* count,
+                           int64_t N)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t L = labels[n];
+        if (!L) continue;
+        const int b = slot_of_root[L - 1];
+        if (b < 0 || !feed[b]) continue;
+        const unsigned int k = atomicAdd(count, 1u);
+        list_node[k] = (uint32_t)n;
+        list_slot[k] = b;
+    }
+}
+
+// ---- merge criterion (Sec. 3.1 eta_m, Sec. 4): one thread per candidate pair -----------------
+template <int Q>
+__device__ __forceinline__ int64_t walk_node(const MergePair& pr, int k, const FieldArgs& a)
+{
+#pragma clang fp contract(off)
+    double pt[3];
+    for (int c = 0; c < 3; ++c) pt[c] = pr.cen_a[c] + pr.dv[c] * (double)k / (double)pr.T;
+    int x = (int)floor(pt[0] + 0.5) % a.nx; if (x < 0) x += a.nx;
+    int y = (int)floor(pt[1] + 0.5) % a.ny; if (y < 0) y += a.ny;
+    int z = 0;
+    if (lat<Q>::d == 3) { z = (int)floor(pt[2] + 0.5) % a.nz; if (z < 0) z += a.nz; }
+    return idx3(x, y, z, a.nx, a.ny);
+}
+
+template <int Q, typename S>
+__global__ void k_merge(const S* f, const uint32_t* labels, const MergePair* pairs,
+                        MergeResult* res, int npairs, int film_max, FieldArgs a)
+{
+    using L = lat<Q>;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    const MergePair pr = pairs[p];
+    MergeResult r;
+    r.fired = 0; r.film_len = -1; r.film_node = -1; r.lap_p = 0.0; r.rho_film = 0.0;
+    // walk (consecutive repeats dropped): last node of a, then first node of b after it
+    int sa = -1, sb = -1, pos = -1;
+    int64_t prev = -1;
+    for (int k = 0; k <= pr.T; ++k) {
+        const int64_t nd = walk_node<Q>(pr, k, a);
+        if (nd == prev) continue;
+        prev = nd;
+        ++pos;
+        if (labels[nd] == pr.label_a) sa = pos;
+    }
+    if (sa >= 0) {
+        prev = -1; pos = -1;
+        for (int k = 0; k <= pr.T && sb < 0; ++k) {
+            const int64_t nd = walk_node<Q>(pr, k, a);
+            if (nd == prev) continue;
+            prev = nd;
+            ++pos;
+            if (pos > sa && labels[nd] == pr.label_b) sb = pos;
+        }
+    }
+    const int len = sb - sa - 1;
+    if (sa >= 0 && sb >= 0 && len >= 1 && len <= film_max) {
+        // film run: positions sa+1 .. sb-1; liquid only; densest node first on ties
+        bool clean = true;
+        int64_t cstar = -1;
+        double best = 0.0;
+        prev = -1; pos = -1;
+        for (int k = 0; k <= pr.T; ++k) {
+            const int64_t nd = walk_node<Q>(pr, k, a);
+            if (nd == prev) continue;
+            prev = nd;
+            ++pos;
+            if (pos <= sa || pos >= sb) continue;
+            if (labels[nd] != 0) clean = false;
+            const double rho = rho_d<Q, S>(f, nd, a);
+            if (cstar < 0 || rho > best) { cstar = nd; best = rho; }
+        }
+        if (clean) {
+            int x, y, z;
+            coords3(cstar, a.nx, a.ny, x, y, z);
+            const double pc = pressure_d(best, a.Gd);
+            double acc = 0.0;
+            for (int i = 1; i < Q; ++i) {
+                const int64_t m = shifted<Q>(x, y, z, i, +1, a);
+                acc += L::wd[i] * (pressure_d(rho_d<Q, S>(f, m, a), a.Gd) - pc);
+            }
+            const double lap = 6.0 * acc;
+            r.film_len = len;
+            r.film_node = cstar;
+            r.lap_p = lap;
+            r.rho_film = best;
+            r.fired = lap >= 0.0 ? 1 : 0;
+        }
+    }
+    res[p] = r;
+}
+
+// ---- blowing-agent source (Sec. 3): f_i(x) += w_i dm_b / n_b on the gas nodes of bubble b ----
+template <int Q, typename S>
+__global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_slot, int64_t count,
+                         const double* add, FieldArgs a)
+{
+    using L = lat<Q>;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double ab = add[list_slot[k]];
+        if (ab == 0.0) continue;
+        const int64_t n = list_node[k];
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            S* slot = f + (int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a);
+            *slot = store_f<S>(load_f(*slot) + (float)(L::wd[i] * ab));
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+// ---- launchers ------------------------------------------------------------------------------
+#define SC_DISPATCH(q, storage, CALL)                                                             \
+    do {                                                                                          \
+        if (q == 9 && storage == SC_STORE_F32) { constexpr int QQ = 9; using SS = float; CALL; }  \
+        else if (q == 9 && storage == SC_STORE_F16) { constexpr int QQ = 9; using SS = _Float16; CALL; } \
+        else if (q == 9 && storage == SC_STORE_BF16) { constexpr int QQ = 9; using SS = __bf16; CALL; } \
+        else if (q == 19 && storage == SC_STORE_F32) { constexpr int QQ = 19; using SS = float; CALL; } \
+        else if (q == 19 && storage == SC_STORE_F16) { constexpr int QQ = 19; using SS = _Float16; CALL; } \
+        else if (q == 19 && storage == SC_STORE_BF16) { constexpr int QQ = 19; using SS = __bf16; CALL; } \
+        else return hipErrorInvalidValue;                                                         \
+    } while (0)
+
+hipError_t launch_psi(int q, int storage, const void* f, double* psi, const FieldArgs& a,
+                      hipStream_t st)
+{
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_psi<QQ, SS>), grid_for(a.N), dim3(256), 0, st,
+                                   (const SS*)f, psi, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int q, int storage, const void* f, const double* psi, float* rho,
+                         float* u, const FieldArgs& a, hipStream_t st)
+{
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_fields<QQ, SS>), grid_for(a.N), dim3(256), 0, st,
+                                   (const SS*)f, psi, rho, u, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_pressure(int q, int storage, const void* f, double* p, const FieldArgs& a,
+                           hipStream_t st)
+{
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_pressure<QQ, SS>), grid_for(a.N), dim3(256), 0, st,
+                                   (const SS*)f, p, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_laplacian(int q, const double* p, double* lap, const FieldArgs& a,
+                            hipStream_t st)
+{
+    if (q == 9)
+        hipLaunchKernelGGL((k_laplacian<9>), grid_for(a.N), dim3(256), 0, st, p, lap, a);
+    else if (q == 19)
+        hipLaunchKernelGGL((k_laplacian<19>), grid_for(a.N), dim3(256), 0, st, p, lap, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(int q, int storage, const void* f, double* partials, double* out_d,
+                         const FieldArgs& a, hipStream_t st)
+{
+    const int nb = totals_blocks(a.N);
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_totals<QQ, SS>), dim3(nb), dim3(256), 0, st, (const SS*)f,
+                                   partials, a));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, partials, nb, out_d,
+                       (double)a.N * a.rho_ref_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_from_rho(int q, int storage, const void* f, uint32_t* parent,
+                                const FieldArgs& a, hipStream_t st)
+{
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_mask_rho<QQ, SS>), grid_for(a.N), dim3(256), 0, st,
+                                   (const SS*)f, parent, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_from_bytes(const uint8_t* mask_d, uint32_t* parent, int64_t N,
+                                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mask_bytes, grid_for(N), dim3(256), 0, st, mask_d, parent, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_union(int q, uint32_t* parent, const FieldArgs& a, hipStream_t st)
+{
+    if (q == 9)
+        hipLaunchKernelGGL((k_union<9>), grid_for(a.N), dim3(256), 0, st, parent, a);
+    else if (q == 19)
+        hipLaunchKernelGGL((k_union<19>), grid_for(a.N), dim3(256), 0, st, parent, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_flatten(uint32_t* parent, uint32_t* labels, uint32_t* ncomp_d, int64_t N,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flatten, grid_for(N), dim3(256), 0, st, parent, labels, ncomp_d, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_labels(const uint32_t* labels, const int64_t* nodes_d, uint32_t* out_d,
+                                int n, int64_t N, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, st, labels, nodes_d, out_d,
+                       n, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_slots(int32_t* slot_of_root, const uint32_t* labs_d, int nb, int clear,
+                            hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_slots, dim3((nb + 255) / 256), dim3(256), 0, st, slot_of_root,
+                       labs_d, nb, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const uint32_t* labels, const int32_t* slot_of_root,
+                        const int32_t* anchors_d, unsigned long long* count_d,
+                        unsigned long long* sums_d, const FieldArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stats, grid_for(a.N), dim3(256), 0, st, labels, slot_of_root, anchors_d,
+                       count_d, sums_d, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gas_list(const uint32_t* labels, const int32_t* slot_of_root,
+                           const int32_t* feed_d, uint32_t* list_node, int32_t* list_slot,
+                           unsigned int* count_d, int64_t N, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gas_list, grid_for(N), dim3(256), 0, st, labels, slot_of_root, feed_d,
+                       list_node, list_slot, count_d, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(int q, int storage, const void* f, const uint32_t* labels,
+                        const MergePair* pairs_d, MergeResult* res_d, int npairs, int film_max,
+                        const FieldArgs& a, hipStream_t st)
+{
+    if (npairs <= 0) return hipSuccess;
+    const dim3 g((npairs + 63) / 64);
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_merge<QQ, SS>), g, dim3(64), 0, st, (const SS*)f, labels,
+                                   pairs_d, res_d, npairs, film_max, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
+                         const int32_t* list_slot, int64_t count, const double* add_d,
+                         const FieldArgs& a, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_source<QQ, SS>), grid_for(count), dim3(256), 0, st, (SS*)f,
+                                   list_node, list_slot, count, add_d, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, grid_for(n), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n,
+                           hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, grid_for(n), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace sc

@@ -1,0 +1,116 @@
+"""C-ABI contract checks that need no GPU: exports, struct layouts, validation errors."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1708_01608_amd import sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sc.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sc.LIB_PATH):
+        from paper_1708_01608_amd import build
+        build.build()
+    return sc.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declarations_match_binding():
+    assert declared_functions() == sorted(sc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version(lib):
+    assert lib.sc_abi_version() == 1
+
+
+def test_params_layout_and_defaults(lib):
+    p = sc.Params()
+    assert lib.sc_params_init(C.byref(p)) == sc.SC_OK
+    assert p.abi_version == 1 and p.lattice == 9 and (p.nx, p.ny, p.nz) == (128, 128, 1)
+    assert p.tau == 1.0 and p.G == -5.0 and p.rho_liquid == 1.93 and p.rho_gas == 0.16
+    assert p.test_every == 10 and p.film_max == 8 and p.storage == 0 and p.rho_ref == -1.0
+
+
+def _c_layout(tmp_path, struct, fields):
+    """offsetof / sizeof of a struct of include/sc.h as the C compiler lays it out."""
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sc.h"', 'int main(void){']
+    lines.append(f'printf("%zu\\n", sizeof({struct}));')
+    for f in fields:
+        lines.append(f'printf("%zu\\n", offsetof({struct}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct,ctype", [("sc_params", sc.Params), ("sc_merge_event", sc.MergeEvent),
+                                          ("sc_topo_event", sc.TopoEvent), ("sc_bubble", sc.Bubble),
+                                          ("sc_allocator", sc.Allocator)])
+def test_binding_structs_match_c_layout(tmp_path, struct, ctype):
+    names = [f[0] for f in ctype._fields_]
+    size, offs = _c_layout(tmp_path, struct, names)
+    assert C.sizeof(ctype) == size
+    assert [getattr(ctype, n).offset for n in names] == offs
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 7), ("lattice", 15), ("nx", 3), ("nz", 2), ("tau", 0.5), ("tau", float("nan")),
+    ("rho_liquid", 0.0), ("noise_amp", -1.0), ("test_every", -1), ("film_max", 0),
+    ("storage", 3), ("tile_x", 48),
+])
+def test_invalid_parameters_are_rejected_before_any_device_work(lib, field, value):
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    setattr(p, field, value)
+    h = C.c_void_p()
+    assert lib.sc_create(C.byref(p), C.byref(h)) == sc.SC_E_INVAL
+    assert not h.value
+    assert lib.sc_last_error()
+
+
+def test_d3q19_needs_depth(lib):
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    p.lattice, p.nz = 19, 1
+    h = C.c_void_p()
+    assert lib.sc_create(C.byref(p), C.byref(h)) == sc.SC_E_INVAL
+
+
+def test_null_handles(lib):
+    assert lib.sc_step(None, 1) == sc.SC_E_INVAL
+    assert lib.sc_destroy(None) == sc.SC_E_INVAL
+    assert lib.sc_fields(None, None, None, None) == sc.SC_E_INVAL
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_library_lattice_is_a_valid_velocity_set(lib, q):
+    e, w = sc.lattice(q)
+    d = 2 if q == 9 else 3
+    assert len({tuple(v) for v in e}) == q
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.abs(w @ e[:, :d]).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib->ab", w, e[:, :d], e[:, :d]) - np.eye(d) / 3).max() < 1e-15
+    # opposite pairs sit next to each other
+    for i in range(1, q, 2):
+        assert np.array_equal(e[i], -e[i + 1])

@@ -1,0 +1,278 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import OracleSim, label_mask
+from paper_1708_01608_amd import sc
+from paper_1708_01608_amd import workloads as W
+from parity import (RHO_TOL, TOL, U_TOL, events_key, field_errors, gpu_from_spec,
+                    oracle_from_spec, permutation_to_oracle)
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+# ---- the two-bubble box (128^2, D2Q9, FP32) ----------------------------------------------------
+@pytest.mark.parametrize("storage,compute", [("f32", "f64"), ("f32", "f32"), ("f16", "f32"),
+                                             ("bf16", "f32")])
+def test_two_bubble_fields_after_100_steps(storage, compute):
+    spec = W.two_bubble()
+    _announce(f"two_bubble 128x128 100 steps storage={storage} compute={compute}")
+    g, o = gpu_from_spec(spec, storage=storage, compute=compute), oracle_from_spec(spec)
+    g.step(100)
+    o.step(100)
+    e_rho, e_u, tg, to = field_errors(g, o)
+    print(f"storage {storage} compute {compute}: rho {e_rho:.3e} u {e_u:.3e} "
+          f"mass {tg[0] / to[0] - 1:.2e}")
+    rt, ut = TOL[(storage, compute)]
+    assert e_rho <= rt and e_u <= ut
+    if (storage, compute) != ("f32", "f64"):
+        return
+    assert abs(tg[0] / to[0] - 1) < 1e-7
+    assert np.array_equal(g.last_labels(), o.labels())
+    gb, ob = g.bubbles(), o.bubbles()
+    assert [(b["label"], b["nucleus"], b["n"]) for b in gb] == \
+           [(b["label"], b["nucleus"], b["n"]) for b in ob]
+    for a, b in zip(gb, ob):
+        assert a["centroid"] == b["centroid"] and a["radius"] == b["radius"]
+
+
+def test_two_bubble_merge_steps_2000():
+    """Criterion step and topological step of the 4-node film, and the full event records."""
+    spec = W.two_bubble()
+    _announce("two_bubble 128x128 2000 steps merge events")
+    g, o = gpu_from_spec(spec), oracle_from_spec(spec)
+    g.step(2000)
+    o.step(2000)
+    eg, eo = g.merge_events(), o.events()
+    print("gpu", eg, "\noracle", eo)
+    assert events_key(eg) == events_key(eo)
+    assert len(eo) == 1
+    for a, b in zip(eg, eo):
+        assert a["lap_p"] == pytest.approx(b["lap_p"], abs=1e-6)
+        assert a["rho_film"] == pytest.approx(b["rho_film"], rel=1e-5)
+    assert g.topo_events() == o.topo_events()
+
+
+@pytest.mark.parametrize("gap", [2, 3, 5])
+def test_gap_sweep_merge_steps(gap):
+    spec = W.two_bubble(gap=gap, steps=400)
+    _announce(f"two_bubble gap {gap} 400 steps")
+    g, o = gpu_from_spec(spec), oracle_from_spec(spec)
+    g.step(400)
+    o.step(400)
+    assert events_key(g.merge_events()) == events_key(o.events())
+    assert g.topo_events() == o.topo_events()
+
+
+# ---- ragged boxes, both lattices, source on --------------------------------------------------------
+@pytest.mark.parametrize("q,shape,tau,tile,compute", [
+    (9, (100, 70, 1), 1.0, None, "f64"), (9, (130, 33, 1), 0.8, (64, 1, 5), "f64"),
+    (19, (40, 36, 20), 0.9, None, "f64"), (19, (35, 18, 13), 1.0, (32, 4, 3), "f64"),
+    (19, (40, 36, 20), 0.9, (64, 4, 7), "f32"),
+])
+def test_ragged_boxes_with_source(q, shape, tau, tile, compute):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx * 7 + ny)
+    n_nuc = 4
+    centres = np.zeros((n_nuc, 3))
+    centres[:, 0] = rng.integers(0, nx, n_nuc)
+    centres[:, 1] = rng.integers(0, ny, n_nuc)
+    if q == 19:
+        centres[:, 2] = rng.integers(0, nz, n_nuc)
+    spec = W.SimSpec(name="ragged", q=q, nx=nx, ny=ny, nz=nz, tau=tau, G=-5.0, amp=1e-3, seed=9,
+                     K=20, centres=centres, radii=np.full(n_nuc, 6.0),
+                     budgets=np.array([5e-3, 1e-1, 0.0, 2e-3]), rate=1e-4)
+    _announce(f"ragged q={q} {shape} tau={tau} tile={tile} compute={compute}")
+    g = gpu_from_spec(spec, tile=tile, compute=compute)
+    o = oracle_from_spec(spec)
+    g.step(100)
+    o.step(100)
+    e_rho, e_u, tg, to = field_errors(g, o)
+    print(f"rho {e_rho:.3e} u {e_u:.3e}")
+    rt, ut = TOL[("f32", compute)]
+    assert e_rho <= rt and e_u <= ut
+    if compute != "f64":
+        return
+    assert abs(tg[0] / to[0] - 1) < 1e-7
+    cg, rg = g.nuclei(n_nuc)
+    co, ro = o.nuclei()
+    assert np.array_equal(cg, co)
+    np.testing.assert_array_equal(rg, ro)  # FP64 bookkeeping, same order
+    assert np.array_equal(g.last_labels(), o.labels())
+    assert events_key(g.merge_events()) == events_key(o.events())
+
+
+# ---- labelling on identical masks ------------------------------------------------------------------
+@pytest.mark.parametrize("q,shape", [(9, (4, 4, 1)), (9, (37, 23, 1)), (9, (256, 128, 1)),
+                                     (19, (8, 8, 8)), (19, (33, 17, 9)), (19, (64, 64, 64))])
+def test_labels_bit_exact_on_identical_masks(q, shape):
+    nx, ny, nz = shape
+    g = sc.Sim(q=q, nx=nx, ny=ny, nz=nz, K=0)
+    rng = np.random.default_rng(nx + ny + nz)
+    for fill in (0.05, 0.3, 0.45, 0.6, 0.9):
+        for _ in range(3 if nx * ny * nz > 10000 else 10):
+            mask = (rng.random(nx * ny * nz) < fill).astype(np.uint8)
+            lg, ng = g.label_bubbles(mask)
+            lo, no = label_mask(q, shape, mask)
+            assert np.array_equal(lg, lo)
+            assert ng == no
+    # degenerate masks: empty, full, one node
+    for mask in (np.zeros(nx * ny * nz, np.uint8), np.ones(nx * ny * nz, np.uint8)):
+        lg, ng = g.label_bubbles(mask)
+        lo, no = label_mask(q, shape, mask)
+        assert np.array_equal(lg, lo) and ng == no
+
+
+def test_labels_all_4x4_masks_sampled():
+    """Every 16th periodic 4x4 mask (4096 masks) against the oracle's flood fill."""
+    g = sc.Sim(q=9, nx=4, ny=4, K=0)
+    for m in range(0, 1 << 16, 16):
+        mask = ((m >> np.arange(16)) & 1).astype(np.uint8)
+        lg, ng = g.label_bubbles(mask)
+        lo, no = label_mask(9, (4, 4, 1), mask)
+        assert np.array_equal(lg, lo) and ng == no, m
+
+
+# ---- EOS, Laplacian and the criterion on synthetic films --------------------------------------------
+@pytest.mark.parametrize("q,shape", [(9, (48, 40, 1)), (19, (24, 20, 16))])
+def test_pressure_laplacian_matches_oracle(q, shape):
+    rng = np.random.default_rng(5)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    rho = rng.uniform(0.15, 2.0, size=N)
+    g = sc.Sim(q=q, nx=nx, ny=ny, nz=nz, K=0)
+    o = OracleSim(q, nx, ny, nz, amp=0.0, K=0)
+    g.set_equilibrium(rho)
+    o.set_equilibrium(rho)
+    pg, lg = g.laplacian_p()
+    po, lo = o.laplacian_p()
+    # the library stores FP32 populations: rho carries one FP32 rounding per population
+    assert np.max(np.abs(pg - po)) < 1e-6
+    assert np.max(np.abs(lg - lo)) < 1e-5
+
+
+@pytest.mark.parametrize("rho_c", [1.10, 1.20, 1.24, 1.33, 1.40, 1.60])
+def test_criterion_on_synthetic_films(rho_c):
+    """Same static film as the oracle pin; the library must fire exactly when the oracle does."""
+    from test_oracle_pins import _film_box
+
+    o, _ = _film_box(rho_c)
+    rho, _, _ = o.fields()
+    g = sc.Sim(q=9, nx=64, ny=16, K=0)
+    g.seed_nuclei(np.array([[15.0, 8.0, 0.0], [31.0, 8.0, 0.0]]), np.array([-1.0, -1.0]),
+                  np.zeros(2), 0.0)
+    g.set_equilibrium(rho)
+    g.test_pass()
+    o.test_pass()
+    assert events_key(g.merge_events()) == events_key(o.events())
+
+
+# ---- full-size workloads at the benchmark's launch configuration -----------------------------------
+def test_foam_2d_full_size_all_nodes():
+    spec = W.foam_2d()
+    _announce("foam_2d 1024^2 20 steps")
+    g, o = gpu_from_spec(spec), oracle_from_spec(spec)
+    g.step(20)
+    o.step(20)
+    e_rho, e_u, tg, to = field_errors(g, o)
+    print(f"rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho <= RHO_TOL and e_u <= U_TOL
+    assert np.array_equal(g.last_labels(), o.labels())
+
+
+def test_foam_3d_full_size_all_nodes():
+    spec = W.foam_3d()
+    _announce("foam_3d 256^3 4 steps (oracle ~1 s/step)")
+    o = oracle_from_spec(spec)
+    o.step(4)
+    for compute in ("f64", "f32"):
+        g = gpu_from_spec(spec, compute=compute)
+        g.step(4)
+        e_rho, e_u, tg, to = field_errors(g, o)
+        print(f"compute {compute}: rho {e_rho:.3e} u {e_u:.3e}")
+        rt, ut = TOL[("f32", compute)]
+        assert e_rho <= rt and e_u <= ut
+        g.close()
+
+
+def test_foam_3d_error_run_16bit_storage():
+    """128^3 box of the 512^3 precision workload: error of every storage type at t = 100."""
+    spec = W.foam_3d_error_run()
+    _announce("foam_3d error run 128^3, 100 steps, f32/f16/bf16 storage")
+    o = oracle_from_spec(spec)
+    o.step(100)
+    for storage, compute in (("f32", "f64"), ("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
+        g = gpu_from_spec(spec, storage=storage, compute=compute)
+        g.step(100)
+        e_rho, e_u, tg, to = field_errors(g, o)
+        print(f"storage {storage} compute {compute}: rho {e_rho:.3e} u {e_u:.3e} "
+              f"mass {tg[0] / to[0] - 1:.2e}")
+        rt, ut = TOL[(storage, compute)]
+        assert e_rho <= rt and e_u <= ut
+        g.close()
+
+
+def test_foam_3d_full_size_conservation_200_steps():
+    spec = W.foam_3d()
+    _announce("foam_3d 256^3 200 steps conservation")
+    g = gpu_from_spec(spec)
+    t0 = g.totals()
+    g.step(200)
+    t1 = g.totals()
+    _, rem = g.nuclei(len(spec.radii))
+    spent = float((spec.budgets - rem).sum())
+    assert abs(t1[0] - (t0[0] + spent)) <= 1e-7 * t0[0]
+    assert np.max(np.abs(t1[1:] - t0[1:])) <= 1e-7 * t0[0]
+
+
+# ---- determinism, state round trip, error latching ---------------------------------------------
+def test_runs_are_bitwise_deterministic():
+    spec = W.two_bubble()
+    a, b = gpu_from_spec(spec), gpu_from_spec(spec)
+    a.step(150)
+    b.step(150)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    assert np.array_equal(a.last_labels(), b.last_labels())
+
+
+@pytest.mark.parametrize("q,shape", [(9, (30, 20, 1)), (19, (12, 10, 8))])
+def test_population_round_trip_and_layout(q, shape):
+    spec = W.SimSpec(name="rt", q=q, nx=shape[0], ny=shape[1], nz=shape[2], K=0)
+    g = gpu_from_spec(spec)
+    o = oracle_from_spec(spec)
+    fg = g.get_populations()
+    fo = o.get_f()
+    perm = permutation_to_oracle(q)
+    # same initial populations up to FP32 rounding, in the library's velocity order
+    assert np.max(np.abs(fg - fo[perm])) < 1e-7
+    g.set_populations(fg)
+    assert np.array_equal(g.get_populations(), fg)
+
+
+def test_numeric_error_latches():
+    g = sc.Sim(q=9, nx=32, ny=32, K=5)
+    f = g.get_populations()
+    f[0, 17] = float("nan")
+    g.set_populations(f)
+    with pytest.raises(sc.ScError) as ei:
+        g.step(5)
+    assert ei.value.code == sc.SC_E_NUMERIC
+    with pytest.raises(sc.ScError) as ei:
+        g.step(1)
+    assert ei.value.code == sc.SC_E_STATE
+
+
+def test_invalid_seed_arguments():
+    g = sc.Sim(q=9, nx=32, ny=32)
+    with pytest.raises(sc.ScError) as ei:
+        g.seed_nuclei(np.zeros((1, 3)), np.array([2.0]), np.array([-1.0]), 1e-4)
+    assert ei.value.code == sc.SC_E_INVAL
+    with pytest.raises(sc.ScError):
+        g.seed_nuclei(np.zeros((1, 3)), np.array([2.0]), np.array([1.0]), float("nan"))
+    g.step(3)  # the handle is still usable

@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--workload", default="foam_3d", choices=WORKLOADS)
     ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
     ap.add_argument("--compute", default="auto", choices=("auto", "f32", "f64"))
-    ap.add_argument("--tile", default=None, help="tx,ty,tz of the step kernel")
+    ap.add_argument("--tile", default=None, help="tx,ty,tz[,variant] of the step kernel")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the step-kernel autotuner (default shape or --tile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0,
                     help="oracle steps timed for cpu_baseline (0: pick ~10-30 s)")
@@ -81,8 +83,13 @@ def run_gpu(spec, args, storage, compute, steps, warmup, tile=None):
 
     from paper_1708_01608_amd import sc
 
-    sim = sc.Sim.from_spec(spec, storage=storage, compute=compute, tile=tile)
+    variant = 0
+    if tile is not None and len(tile) == 4:
+        tile, variant = tile[:3], tile[3]
+    sim = sc.Sim.from_spec(spec, storage=storage, compute=compute, tile=tile, variant=variant)
     sim.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
+    if tile is None and not args.no_autotune:
+        sim.autotune(trials=3)
     K = spec.K
     for _ in range(warmup):
         sim.step(K)
@@ -173,6 +180,7 @@ def main():
             "test_every": spec.K,
             "lattice_steps_per_step": spec.K,
             "step_tile": list(r["tile"]),
+            "autotuned": args.tile is None and not args.no_autotune,
         },
         "roofline": {
             "bound": "hbm",

@@ -81,7 +81,7 @@ typedef struct sc_params {
     void* stream;              /* hipStream_t to run on; NULL: the library creates one */
     const sc_allocator* allocator; /* NULL: hipMalloc / hipFree */
     int32_t tile_x, tile_y, tile_z; /* step-kernel tile; 0 selects the tuned default */
-    int32_t reserved1;
+    int32_t step_variant;      /* 0 default, 1 plain marching, 2 software-pipelined (D3Q19) */
 } sc_params;
 
 /* One firing of the merge criterion (Sec. 3.1 eta_m: 1 -> 0; Sec. 4 film rupture). */
@@ -188,11 +188,65 @@ int sc_test_pass(struct sc_sim* sim);
 int sc_profile(struct sc_sim* sim, int32_t enable);
 int sc_profile_read(struct sc_sim* sim, int32_t kernel_class, double* ms, int64_t* launches);
 
+/* Autotuner of the step kernel.  Times every candidate (tile_x, tile_y, tile_z, variant) on the
+ * current state with HIP events -- each trial launch reads the current populations and writes the
+ * spare buffer, so the simulation is unchanged -- and keeps the fastest for this handle.  The
+ * choice is remembered for later handles of the same lattice, box, storage and compute type in
+ * this process.  trials >= 1 launches per candidate; out[cap] (may be NULL) receives the timings
+ * in candidate order, *n_out the candidate count. */
+typedef struct sc_tune_entry {
+    int32_t tile_x, tile_y, tile_z, variant;
+    double us_per_launch;
+} sc_tune_entry;
+int sc_autotune(struct sc_sim* sim, int32_t trials, sc_tune_entry* out, int32_t cap,
+                int32_t* n_out);
+
 /* Tile shape and compute type chosen for the step kernel (after tuning or from sc_params). */
-int sc_step_config(struct sc_sim* sim, int32_t* tile_x, int32_t* tile_y, int32_t* tile_z);
+int sc_step_config(struct sc_sim* sim, int32_t* tile_x, int32_t* tile_y, int32_t* tile_z,
+                   int32_t* variant);
 int sc_compute_type(struct sc_sim* sim, int32_t* compute);
 
+/* ---- batch of independent two-bubble D2Q9 boxes (Sec. 4 two-bubble merging, Fig. 3 sizes) ----
+ * Every box is filled with liquid plus noise and two gas balls as sc_create + sc_seed_nuclei
+ * would (no blowing-agent source), then stepped, with a test pass every test_every steps, until
+ * the merge criterion fires, the two nuclei share one gas component, or max_steps.  All boxes run
+ * in one persistent kernel launch (captured once in a HIP graph) fed by a work queue; storage is
+ * FP32, arithmetic FP64 (AUTO/F64) or FP32. */
+typedef struct sc_batch_instance {
+    int32_t nx, ny;            /* 4 <= nx <= 256, ny >= 4, periodic */
+    double tau, G;
+    double rho_liquid, rho_gas, noise_amp;
+    uint64_t noise_seed;
+    double gas_threshold;      /* <= 0: (rho_liquid + rho_gas)/2 */
+    double centre[2][3];       /* the two nuclei (z ignored) */
+    double radius[2];
+} sc_batch_instance;
+
+typedef struct sc_batch_result {
+    int64_t merge_step;        /* step of the criterion firing, -1 if none */
+    int64_t topo_step;         /* first test step with both nuclei in one component, -1 if none */
+    int64_t steps_run;
+    int64_t film_node;         /* c* of the firing (-1 if none) */
+    int32_t film_len;
+    int32_t status;            /* SC_OK, or SC_E_NUMERIC if a total was not finite */
+    double lap_p, rho_film;
+    double totals[3];          /* FP64 mass and momentum at the last test pass */
+} sc_batch_result;
+
+/* Copies the instance table; allocates [2][9][N] FP32 populations and N labels per box.
+ * Errors: SC_E_INVAL (a box outside the limits above), SC_E_NOMEM, SC_E_DEVICE. */
+int sc_batch_create(int32_t n, const sc_batch_instance* inst, int32_t test_every,
+                    int32_t film_max, int32_t max_steps, int32_t compute, void* stream,
+                    const sc_allocator* allocator, struct sc_batch** out);
+/* Runs every box from its initial state (repeatable); results[n] may be NULL; *kernel_ms gets
+ * the HIP-event time of the launch.  Synchronous. */
+int sc_batch_run(struct sc_batch* b, sc_batch_result* results, double* kernel_ms);
+/* FP32 density of box k after the last run (FP64 sums of the stored populations). */
+int sc_batch_fields(struct sc_batch* b, int32_t k, float* rho);
+int sc_batch_destroy(struct sc_batch* b);
+
 typedef struct sc_sim sc_sim;
+typedef struct sc_batch sc_batch;
 
 #ifdef __cplusplus
 }

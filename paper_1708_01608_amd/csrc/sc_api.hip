@@ -7,7 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sc_internal.hpp"
@@ -35,6 +38,8 @@ struct ProfRec {
 };
 
 }  // namespace
+
+int sc::set_error(int code, const std::string& msg) { return fail(code, msg); }
 
 struct sc_sim {
     sc_params p;
@@ -179,6 +184,7 @@ InitArgs init_args(const sc_sim* s, double rho)
 StepShape default_shape(const sc_params& p)
 {
     StepShape sh;
+    sh.variant = 1;
     if (p.lattice == SC_D2Q9) {
         sh.tile_x = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
         sh.tile_y = 1;
@@ -190,6 +196,43 @@ StepShape default_shape(const sc_params& p)
         sh.tile_y = 8;
         sh.tile_z = 16;
     }
+    return sh;
+}
+
+// Shapes chosen by sc_autotune, per (lattice, nx, ny, nz, storage, compute), for this process.
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, StepShape> g_tuned;
+
+TuneKey tune_key(const sc_params& p, int compute)
+{
+    return TuneKey{p.lattice, p.nx, p.ny, p.nz, p.storage, compute};
+}
+
+std::vector<StepShape> tune_candidates(int q)
+{
+    std::vector<StepShape> c;
+    if (q == SC_D2Q9) {
+        for (int tx : {64, 128, 256, 512})
+            for (int tz : {2, 4, 8, 16, 32, 64}) c.push_back(StepShape{tx, 1, tz, 1});
+    } else {
+        const int tiles[][2] = {{32, 4}, {32, 8}, {32, 16}, {64, 4}, {64, 8}, {128, 4}, {16, 16}};
+        for (auto& t : tiles)
+            for (int tz : {8, 16, 32, 64})
+                for (int v : {1, 2}) c.push_back(StepShape{t[0], t[1], tz, v});
+    }
+    return c;
+}
+
+// Explicit tile and variant from the parameters, defaults filling the fields left at zero.
+StepShape shape_from_params(const sc_params& p)
+{
+    StepShape sh = default_shape(p);
+    if (p.tile_x) sh.tile_x = p.tile_x;
+    if (p.tile_y) sh.tile_y = p.tile_y;
+    if (p.lattice == SC_D2Q9) sh.tile_y = 1;
+    if (p.tile_z) sh.tile_z = p.tile_z;
+    if (p.step_variant) sh.variant = p.step_variant;
     return sh;
 }
 
@@ -588,8 +631,8 @@ int validate(const sc_params* p)
     if (!std::isfinite(p->rho_ref)) return fail(SC_E_INVAL, "rho_ref must be finite");
     if (p->allocator && (!p->allocator->alloc || !p->allocator->free))
         return fail(SC_E_INVAL, "allocator needs alloc and free");
-    if (p->tile_x || p->tile_y || p->tile_z) {
-        StepShape sh{p->tile_x, p->lattice == SC_D2Q9 ? 1 : p->tile_y, p->tile_z};
+    if (p->tile_x || p->tile_y || p->tile_z || p->step_variant) {
+        StepShape sh = shape_from_params(*p);
         if (!step_shape_supported(p->lattice, sh)) return fail(SC_E_INVAL, "unsupported step tile");
     }
     return SC_OK;
@@ -661,10 +704,12 @@ int sc_create(const sc_params* p, sc_sim** out)
     s->compute = p->compute != SC_COMPUTE_AUTO
                      ? p->compute
                      : (p->storage == SC_STORE_F32 ? SC_COMPUTE_F64 : SC_COMPUTE_F32);
-    if (p->tile_x || p->tile_y || p->tile_z)
-        s->shape = StepShape{p->tile_x, p->lattice == SC_D2Q9 ? 1 : p->tile_y, p->tile_z};
-    else
-        s->shape = default_shape(*p);
+    s->shape = shape_from_params(*p);
+    if (!(p->tile_x || p->tile_y || p->tile_z || p->step_variant)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(tune_key(*p, s->compute));
+        if (it != g_tuned.end()) s->shape = it->second;
+    }
     if (p->stream) {
         s->stream = (hipStream_t)p->stream;
     } else {
@@ -1016,6 +1061,62 @@ int sc_profile_read(sc_sim* s, int32_t cls, double* ms, int64_t* launches)
     return SC_OK;
 }
 
+int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int32_t* n_out)
+{
+    TRY(check_usable(s));
+    if (trials < 1 || cap < 0 || (cap > 0 && !out)) return fail(SC_E_INVAL, "bad autotune arguments");
+    StepArgs a;
+    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
+    a.N = s->N;
+    a.tau = (float)s->p.tau; a.omega = (float)(1.0 / s->p.tau);
+    a.G = (float)s->p.G; a.rho_ref = (float)s->rho_ref;
+    a.taud = s->p.tau; a.omegad = 1.0 / s->p.tau; a.Gd = s->p.G; a.rho_refd = s->rho_ref;
+    const std::vector<StepShape> cand = tune_candidates(s->q);
+    hipEvent_t e0, e1;
+    HIPX(hipEventCreate(&e0));
+    HIPX(hipEventCreate(&e1));
+    double best = 1e300;
+    StepShape best_shape = s->shape;
+    int k = 0;
+    int rc = SC_OK;
+    for (const StepShape& sh : cand) {
+        if (!step_shape_supported(s->q, sh)) continue;
+        a.planes = sh.tile_z;
+        // one untimed launch, then `trials` timed launches current -> spare buffer
+        hipError_t e = launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1],
+                                   a, sh, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+        for (int r = 0; r < trials && e == hipSuccess; ++r)
+            e = launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a, sh,
+                            s->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = device_fail(s, e, "autotune trial");
+            break;
+        }
+        const double us = 1e3 * ms / trials;
+        if (k < cap) out[k] = sc_tune_entry{sh.tile_x, sh.tile_y, sh.tile_z, sh.variant, us};
+        ++k;
+        if (us < best) {
+            best = us;
+            best_shape = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SC_OK) return rc;
+    s->shape = best_shape;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[tune_key(s->p, s->compute)] = best_shape;
+    }
+    if (n_out) *n_out = k;
+    return SC_OK;
+}
+
 int sc_compute_type(sc_sim* s, int32_t* compute)
 {
     if (!s || !compute) return fail(SC_E_INVAL, "NULL argument");
@@ -1023,12 +1124,13 @@ int sc_compute_type(sc_sim* s, int32_t* compute)
     return SC_OK;
 }
 
-int sc_step_config(sc_sim* s, int32_t* tx, int32_t* ty, int32_t* tz)
+int sc_step_config(sc_sim* s, int32_t* tx, int32_t* ty, int32_t* tz, int32_t* variant)
 {
     if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
     if (tx) *tx = s->shape.tile_x;
     if (ty) *ty = s->shape.tile_y;
     if (tz) *tz = s->shape.tile_z;
+    if (variant) *variant = s->shape.variant;
     return SC_OK;
 }
 

@@ -4,9 +4,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "sc.h"
 
 namespace sc {
+
+// Records the calling thread's error message (returned by sc_last_error) and returns code.
+int set_error(int code, const std::string& msg);
 
 // Arguments of the fused step kernel.
 struct StepArgs {
@@ -19,6 +24,7 @@ struct StepArgs {
 
 struct StepShape {
     int tile_x, tile_y, tile_z;  // tile_y is 1 in 2D; tile_z = planes per block
+    int variant;                 // 1: plain marching kernel, 2: software-pipelined (3D only)
 };
 
 // storage codes as in sc.h: 0 F32, 1 F16, 2 BF16

@@ -18,6 +18,7 @@
 // per plane separate writers from readers.
 #include "sc_device.hpp"
 #include "sc_internal.hpp"
+#include "sc_stepcore.hpp"
 
 namespace sc {
 
@@ -37,86 +38,6 @@ __device__ __forceinline__ int logical_block(const StepGrid& g)
     const int n = g.gx * g.gy * g.gz;
     if (!g.remap) return b;
     return (b & 7) * (n >> 3) + (b >> 3);
-}
-
-template <int Q, typename S>
-__device__ __forceinline__ void pull_node(const S* __restrict__ src, int64_t N, int nx, int ny,
-                                          int x, int xm, int xp, int y, int ym, int yp, int z,
-                                          int zm, int zp, float* g)
-{
-    using L = lat<Q>;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int sx = L::ex[i] > 0 ? xm : (L::ex[i] < 0 ? xp : x);
-        const int sy = L::ey[i] > 0 ? ym : (L::ey[i] < 0 ? yp : y);
-        const int sz = L::ez[i] > 0 ? zm : (L::ez[i] < 0 ? zp : z);
-        const S* base = src + (int64_t)i * N;
-        g[i] = load_f(base[sx + nx * (sy + ny * sz)]);
-    }
-}
-
-// Deviation sum sum_i g_i in the arithmetic type A (fixed order: the ring and the owner of a
-// node obtain the same value).
-template <int Q, typename A>
-__device__ __forceinline__ A sum_dev(const float* g)
-{
-    A s = (A)0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) s += (A)g[i];
-    return s;
-}
-
-// Scalar coefficients in the arithmetic type.
-template <typename A>
-struct Coef {
-    A tau, omega, G, rho_ref;
-};
-__device__ __forceinline__ Coef<float> coef_of(const StepArgs& a, float)
-{
-    return Coef<float>{a.tau, a.omega, a.G, a.rho_ref};
-}
-__device__ __forceinline__ Coef<double> coef_of(const StepArgs& a, double)
-{
-    return Coef<double>{a.taud, a.omegad, a.Gd, a.rho_refd};
-}
-
-// Forced BGK collision on deviations g_i = f_i - w_i rho_ref; writes f_i* - w_i rho_ref.
-// With h_i = g_i - w_i drho (one fused rounding), the relaxation
-//   f_i* = f_i - (f_i - f_i^eq)/tau,  f_i^eq - w_i rho_ref = w_i drho + w_i rho P_i,
-//   P_i = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2,
-// becomes g_i* = g_i + omega (w_i rho P_i - h_i): every intermediate is small, so rounding
-// happens at the scale of the non-equilibrium part instead of w_i rho.
-template <int Q, typename A, typename S>
-__device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, int idx,
-                                              const float* g, A drho, A Fx, A Fy, A Fz,
-                                              const Coef<A>& c)
-{
-    using L = lat<Q>;
-    const A rho = c.rho_ref + drho;
-    A jx = (A)0, jy = (A)0, jz = (A)0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (L::ex[i] > 0) jx += (A)g[i]; else if (L::ex[i] < 0) jx -= (A)g[i];
-        if (L::ey[i] > 0) jy += (A)g[i]; else if (L::ey[i] < 0) jy -= (A)g[i];
-        if (L::ez[i] > 0) jz += (A)g[i]; else if (L::ez[i] < 0) jz -= (A)g[i];
-    }
-    const A inv = (A)1 / rho;
-    // velocity-shift forcing: u_eq = (j + tau F) / rho
-    const A ux = fmad(c.tau, Fx, jx) * inv;
-    const A uy = fmad(c.tau, Fy, jy) * inv;
-    const A uz = fmad(c.tau, Fz, jz) * inv;
-    const A usq15 = (A)1.5 * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const A eu = (A)L::ex[i] * ux + (A)L::ey[i] * uy + (A)L::ez[i] * uz;
-        const A P = fmad(eu, fmad((A)4.5, eu, (A)3), -usq15);
-        const A w = weight<Q, A>(i);
-        const A gi = (A)g[i];
-        const A h = fmad(-w, drho, gi);
-        const A d = fmad(w * rho, P, -h);
-        const A gs = fmad(c.omega, d, gi);
-        dst[(int64_t)i * N + idx] = store_f<S>((float)gs);
-    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -333,11 +254,136 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
 }
 
 // ------------------------------------------------------------------------------------------
+// D3Q19, software-pipelined: the loads of plane z+2 are issued before plane z is collided, so a
+// wave keeps a plane of loads in flight through its collision and stores.  Ring nodes are spread
+// evenly over the waves of the block (ring node r -> wave r % W, lane r / W), so no wave carries
+// the whole ring.  Iteration z reads psi slots of planes z-1, z, z+1 and writes plane z+2's slot
+// after its collision; the one barrier at the end of the iteration separates writers from readers
+// (plane z-2's slot, overwritten now, was last read before the previous barrier).
+// ------------------------------------------------------------------------------------------
+template <typename S, typename A, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ src,
+                                                        S* __restrict__ dst, StepArgs a,
+                                                        StepGrid grid)
+{
+    using L = lat<19>;
+    constexpr int NW = (TX * TY) / 64;
+    __shared__ A ps[4][TY + 2][TX + 2];
+    const Coef<A> c = coef_of(a, A());
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t N = a.N;
+    const int lb = logical_block(grid);
+    const int bx = lb % grid.gx;
+    const int by = (lb / grid.gx) % grid.gy;
+    const int bz = lb / (grid.gx * grid.gy);
+    const int t = threadIdx.x;
+    const int tx = t % TX, ty = t / TX;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * a.planes;
+    const int wx = min(TX, nx - x0), wy = min(TY, ny - y0);
+    const int ze = min(z0 + a.planes, nz);
+    const bool own = tx < wx && ty < wy;
+    const int x = x0 + (own ? tx : 0), y = y0 + (own ? ty : 0);
+    const int xm = wrap_once(x - 1, nx), xp = wrap_once(x + 1, nx);
+    const int ym = wrap_once(y - 1, ny), yp = wrap_once(y + 1, ny);
+
+    const int nring = 2 * (wx + 2) + 2 * wy;
+    const int r = (t & 63) * NW + (t >> 6);
+    const bool ring = r < nring;
+    int hlx, hly;
+    if (r < wx + 2) {
+        hlx = r; hly = 0;
+    } else if (r < 2 * (wx + 2)) {
+        hlx = r - (wx + 2); hly = wy + 1;
+    } else if (r < 2 * (wx + 2) + wy) {
+        hlx = 0; hly = 1 + r - 2 * (wx + 2);
+    } else {
+        hlx = wx + 1; hly = 1 + r - 2 * (wx + 2) - wy;
+    }
+    const int hx = wrap_once(x0 - 1 + (ring ? hlx : 1), nx);
+    const int hy = wrap_once(y0 - 1 + (ring ? hly : 1), ny);
+    const int hxm = wrap_once(hx - 1, nx), hxp = wrap_once(hx + 1, nx);
+    const int hym = wrap_once(hy - 1, ny), hyp = wrap_once(hy + 1, ny);
+
+    float cur[19], nxt[19], pre[19], hpre[19];
+    A dcur = (A)0, dnxt = (A)0;
+
+    // planes z0-1 (psi), z0 (psi + cur), z0+1 (psi + nxt)
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+        const int z = wrap_once(z0 - 1 + k, nz);
+        const int zm = wrap_once(z - 1, nz), zp = wrap_once(z + 1, nz);
+        if (own) {
+            pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z, zm, zp, pre);
+            const A d = sum_dev<19, A>(pre);
+            ps[k][ty + 1][tx + 1] = psi_f(c.rho_ref + d);
+            if (k == 1) {
+#pragma unroll
+                for (int i = 0; i < 19; ++i) cur[i] = pre[i];
+                dcur = d;
+            } else if (k == 2) {
+#pragma unroll
+                for (int i = 0; i < 19; ++i) nxt[i] = pre[i];
+                dnxt = d;
+            }
+        }
+        if (ring) {
+            pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z, zm, zp, hpre);
+            ps[k][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(hpre));
+        }
+    }
+    __syncthreads();
+
+    for (int z = z0; z < ze; ++z) {
+        const int s = (z - z0 + 1) & 3;
+        const int sn = (s + 1) & 3, sp = (s + 3) & 3, s2 = (s + 2) & 3;
+        const bool more = z + 1 < ze;  // plane z+2 is needed by the collision of plane z+1
+        if (more) {
+            const int z2 = wrap_once(z + 2 >= nz ? z + 2 - nz : z + 2, nz);
+            const int zm = wrap_once(z2 - 1, nz), zp = wrap_once(z2 + 1, nz);
+            if (own) pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z2, zm, zp, pre);
+            if (ring) pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z2, zm, zp, hpre);
+        }
+        if (own) {
+            const A pc = ps[s][ty + 1][tx + 1];
+            A fx = (A)0, fy = (A)0, fz = (A)0;
+#pragma unroll
+            for (int i = 1; i < 19; ++i) {
+                const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
+                const A pn = weight<19, A>(i) * ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
+                if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
+                if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
+                if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
+            }
+            const A gp = -c.G * pc;
+            collide_store<19, A, S>(dst, N, x + nx * (y + ny * z), cur, dcur, gp * fx, gp * fy,
+                                    gp * fz, c);
+        }
+        A dpre = (A)0;
+        if (more) {
+            if (own) {
+                dpre = sum_dev<19, A>(pre);
+                ps[s2][ty + 1][tx + 1] = psi_f(c.rho_ref + dpre);
+            }
+            if (ring) ps[s2][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(hpre));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            cur[i] = nxt[i];
+            nxt[i] = pre[i];
+        }
+        dcur = dnxt;
+        dnxt = dpre;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Launch
 // ------------------------------------------------------------------------------------------
 bool step_shape_supported(int q, const StepShape& s)
 {
     if (s.tile_z < 1) return false;
+    if (s.variant < 0 || s.variant > 2 || (q == 9 && s.variant == 2)) return false;
     if (q == 9) return s.tile_y == 1 && (s.tile_x == 64 || s.tile_x == 128 || s.tile_x == 256 ||
                                           s.tile_x == 512);
     if (q == 19) {
@@ -374,8 +420,12 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
     }
 #define SC_L3(TX, TY)                                                                            \
     if (s.tile_x == TX && s.tile_y == TY) {                                                      \
-        hipLaunchKernelGGL((k_step3d<S, A, TX, TY>), grid, dim3(TX * TY), 0, st, src, dst, a,    \
-                           g);                                                                   \
+        if (s.variant == 2)                                                                      \
+            hipLaunchKernelGGL((k_step3d_pipe<S, A, TX, TY>), grid, dim3(TX * TY), 0, st, src,   \
+                               dst, a, g);                                                       \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_step3d<S, A, TX, TY>), grid, dim3(TX * TY), 0, st, src, dst,   \
+                               a, g);                                                            \
         return hipGetLastError();                                                                \
     }
     if (q == 9) {

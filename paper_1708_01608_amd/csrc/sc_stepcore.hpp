@@ -1,0 +1,90 @@
+// sc_stepcore.hpp -- per-node pieces of the Shan-Chen step shared by the single-box and the
+// batched kernels: pulled loads, deviation sums, and the forced BGK collision.
+#pragma once
+
+#include "sc_device.hpp"
+#include "sc_internal.hpp"
+
+namespace sc {
+
+template <int Q, typename S>
+__device__ __forceinline__ void pull_node(const S* __restrict__ src, int64_t N, int nx, int ny,
+                                          int x, int xm, int xp, int y, int ym, int yp, int z,
+                                          int zm, int zp, float* g)
+{
+    using L = lat<Q>;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int sx = L::ex[i] > 0 ? xm : (L::ex[i] < 0 ? xp : x);
+        const int sy = L::ey[i] > 0 ? ym : (L::ey[i] < 0 ? yp : y);
+        const int sz = L::ez[i] > 0 ? zm : (L::ez[i] < 0 ? zp : z);
+        const S* base = src + (int64_t)i * N;
+        g[i] = load_f(base[sx + nx * (sy + ny * sz)]);
+    }
+}
+
+// Deviation sum sum_i g_i in the arithmetic type A (fixed order: the ring and the owner of a
+// node obtain the same value).
+template <int Q, typename A>
+__device__ __forceinline__ A sum_dev(const float* g)
+{
+    A s = (A)0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += (A)g[i];
+    return s;
+}
+
+// Scalar coefficients in the arithmetic type.
+template <typename A>
+struct Coef {
+    A tau, omega, G, rho_ref;
+};
+__device__ __forceinline__ Coef<float> coef_of(const StepArgs& a, float)
+{
+    return Coef<float>{a.tau, a.omega, a.G, a.rho_ref};
+}
+__device__ __forceinline__ Coef<double> coef_of(const StepArgs& a, double)
+{
+    return Coef<double>{a.taud, a.omegad, a.Gd, a.rho_refd};
+}
+
+// Forced BGK collision on deviations g_i = f_i - w_i rho_ref; writes f_i* - w_i rho_ref.
+// With h_i = g_i - w_i drho (one fused rounding), the relaxation
+//   f_i* = f_i - (f_i - f_i^eq)/tau,  f_i^eq - w_i rho_ref = w_i drho + w_i rho P_i,
+//   P_i = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2,
+// becomes g_i* = g_i + omega (w_i rho P_i - h_i): every intermediate is small, so rounding
+// happens at the scale of the non-equilibrium part instead of w_i rho.
+template <int Q, typename A, typename S>
+__device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, int idx,
+                                              const float* g, A drho, A Fx, A Fy, A Fz,
+                                              const Coef<A>& c)
+{
+    using L = lat<Q>;
+    const A rho = c.rho_ref + drho;
+    A jx = (A)0, jy = (A)0, jz = (A)0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (L::ex[i] > 0) jx += (A)g[i]; else if (L::ex[i] < 0) jx -= (A)g[i];
+        if (L::ey[i] > 0) jy += (A)g[i]; else if (L::ey[i] < 0) jy -= (A)g[i];
+        if (L::ez[i] > 0) jz += (A)g[i]; else if (L::ez[i] < 0) jz -= (A)g[i];
+    }
+    const A inv = (A)1 / rho;
+    // velocity-shift forcing: u_eq = (j + tau F) / rho
+    const A ux = fmad(c.tau, Fx, jx) * inv;
+    const A uy = fmad(c.tau, Fy, jy) * inv;
+    const A uz = fmad(c.tau, Fz, jz) * inv;
+    const A usq15 = (A)1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const A eu = (A)L::ex[i] * ux + (A)L::ey[i] * uy + (A)L::ez[i] * uz;
+        const A P = fmad(eu, fmad((A)4.5, eu, (A)3), -usq15);
+        const A w = weight<Q, A>(i);
+        const A gi = (A)g[i];
+        const A h = fmad(-w, drho, gi);
+        const A d = fmad(w * rho, P, -h);
+        const A gs = fmad(c.omega, d, gi);
+        dst[(int64_t)i * N + idx] = store_f<S>((float)gs);
+    }
+}
+
+}  // namespace sc

@@ -43,7 +43,7 @@ class Params(C.Structure):
         ("film_max", C.c_int32), ("storage", C.c_int32), ("compute", C.c_int32),
         ("rho_ref", C.c_double), ("stream", C.c_void_p), ("allocator", C.POINTER(Allocator)),
         ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
-        ("reserved1", C.c_int32),
+        ("step_variant", C.c_int32),
     ]
 
 
@@ -68,6 +68,28 @@ class Bubble(C.Structure):
     ]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
+                ("variant", C.c_int32), ("us_per_launch", C.c_double)]
+
+
+class BatchInstance(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("tau", C.c_double), ("G", C.c_double),
+        ("rho_liquid", C.c_double), ("rho_gas", C.c_double), ("noise_amp", C.c_double),
+        ("noise_seed", C.c_uint64), ("gas_threshold", C.c_double),
+        ("centre", (C.c_double * 3) * 2), ("radius", C.c_double * 2),
+    ]
+
+
+class BatchResult(C.Structure):
+    _fields_ = [
+        ("merge_step", C.c_int64), ("topo_step", C.c_int64), ("steps_run", C.c_int64),
+        ("film_node", C.c_int64), ("film_len", C.c_int32), ("status", C.c_int32),
+        ("lap_p", C.c_double), ("rho_film", C.c_double), ("totals", C.c_double * 3),
+    ]
+
+
 # Entry points declared in include/sc.h (checked by the CPU test suite).
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
@@ -75,6 +97,7 @@ EXPORTS = (
     "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_time",
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
+    "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
 )
 
 _lib = None
@@ -119,8 +142,14 @@ def load_library(path=LIB_PATH):
         "sc_test_pass": (C.c_int, [P]),
         "sc_profile": (C.c_int, [P, C.c_int32]),
         "sc_profile_read": (C.c_int, [P, C.c_int32, P, P]),
-        "sc_step_config": (C.c_int, [P, P, P, P]),
+        "sc_step_config": (C.c_int, [P, P, P, P, P]),
         "sc_compute_type": (C.c_int, [P, P]),
+        "sc_batch_create": (C.c_int, [C.c_int32, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      P, P, C.POINTER(C.c_void_p)]),
+        "sc_batch_run": (C.c_int, [P, P, P]),
+        "sc_batch_fields": (C.c_int, [P, C.c_int32, P]),
+        "sc_batch_destroy": (C.c_int, [P]),
+        "sc_autotune": (C.c_int, [P, C.c_int32, P, C.c_int32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -178,7 +207,7 @@ class Sim:
 
     def __init__(self, q=9, nx=128, ny=128, nz=1, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16,
                  amp=1e-3, seed=1, theta=0.0, K=10, film_max=8, storage="f32", compute="auto",
-                 rho_ref=-1.0, tile=None, memory="torch"):
+                 rho_ref=-1.0, tile=None, variant=0, memory="torch"):
         self._lib = load_library()
         self._h = None
         p = Params()
@@ -192,6 +221,7 @@ class Sim:
         p.rho_ref = rho_ref
         if tile is not None:
             p.tile_x, p.tile_y, p.tile_z = tile
+        p.step_variant = int(variant)
         self.mem = None
         if memory == "torch":
             self.mem = TorchMemory()
@@ -324,9 +354,19 @@ class Sim:
         return ms.value, n.value
 
     def step_config(self):
-        v = [C.c_int32() for _ in range(3)]
+        v = [C.c_int32() for _ in range(4)]
         _check(self._lib.sc_step_config(self._h, *[C.byref(x) for x in v]))
         return tuple(x.value for x in v)
+
+    def autotune(self, trials=5):
+        """Times every step-kernel candidate on the current state, keeps the fastest."""
+        cap = 128
+        arr = (TuneEntry * cap)()
+        n = C.c_int32()
+        _check(self._lib.sc_autotune(self._h, int(trials), C.cast(arr, C.c_void_p), cap,
+                                     C.byref(n)))
+        return [dict(tile=(e.tile_x, e.tile_y, e.tile_z), variant=e.variant,
+                     us=e.us_per_launch) for e in arr[: n.value]]
 
     def compute_type(self):
         v = C.c_int32()
@@ -336,3 +376,60 @@ class Sim:
     @property
     def stream(self):
         return None if self.mem is None else self.mem.stream
+
+
+class Batch:
+    """Independent two-bubble D2Q9 boxes run by one persistent kernel (sc_batch_*)."""
+
+    def __init__(self, spec, compute="auto", max_steps=None, memory="torch"):
+        """spec: workloads.BatchSpec."""
+        self._lib = load_library()
+        self._h = None
+        n = spec.n
+        arr = (BatchInstance * n)()
+        for k in range(n):
+            s = spec.instance(k)
+            I = arr[k]
+            I.nx, I.ny, I.tau, I.G = s.nx, s.ny, s.tau, s.G
+            I.rho_liquid, I.rho_gas, I.noise_amp, I.noise_seed = s.rho_l, s.rho_g, s.amp, s.seed
+            I.gas_threshold = s.theta
+            for b in range(2):
+                for c in range(3):
+                    I.centre[b][c] = float(s.centres[b][c])
+                I.radius[b] = float(s.radii[b])
+        self.n = n
+        self.spec = spec
+        self.mem = TorchMemory() if memory == "torch" else None
+        stream = self.mem.stream.cuda_stream if self.mem else None
+        alloc = C.pointer(self.mem.struct) if self.mem else None
+        h = C.c_void_p()
+        ms = spec.max_steps if max_steps is None else max_steps
+        _check(self._lib.sc_batch_create(n, C.cast(arr, C.c_void_p), spec.K, spec.film_max, ms,
+                                         COMPUTE[compute], stream, alloc, C.byref(h)))
+        self._h = h
+
+    def run(self):
+        res = (BatchResult * self.n)()
+        ms = C.c_double()
+        _check(self._lib.sc_batch_run(self._h, C.cast(res, C.c_void_p), C.byref(ms)))
+        out = [dict(merge_step=r.merge_step, topo_step=r.topo_step, steps_run=r.steps_run,
+                    film_node=r.film_node, film_len=r.film_len, status=r.status, lap_p=r.lap_p,
+                    rho_film=r.rho_film, totals=tuple(r.totals)) for r in res]
+        return out, ms.value
+
+    def density(self, k):
+        nx, ny = int(self.spec.nx[k]), int(self.spec.ny[k])
+        rho = np.zeros(nx * ny, dtype=np.float32)
+        _check(self._lib.sc_batch_fields(self._h, int(k), _ptr(rho)))
+        return rho
+
+    def close(self):
+        if self._h is not None:
+            self._lib.sc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

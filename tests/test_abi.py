@@ -66,7 +66,10 @@ def _c_layout(tmp_path, struct, fields):
 
 @pytest.mark.parametrize("struct,ctype", [("sc_params", sc.Params), ("sc_merge_event", sc.MergeEvent),
                                           ("sc_topo_event", sc.TopoEvent), ("sc_bubble", sc.Bubble),
-                                          ("sc_allocator", sc.Allocator)])
+                                          ("sc_allocator", sc.Allocator),
+                                          ("sc_batch_instance", sc.BatchInstance),
+                                          ("sc_batch_result", sc.BatchResult),
+                                          ("sc_tune_entry", sc.TuneEntry)])
 def test_binding_structs_match_c_layout(tmp_path, struct, ctype):
     names = [f[0] for f in ctype._fields_]
     size, offs = _c_layout(tmp_path, struct, names)

@@ -1,0 +1,82 @@
+"""GPU parity of the batched two-bubble boxes (one persistent launch) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import OracleSim
+from paper_1708_01608_amd import sc
+from paper_1708_01608_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_run(s, max_steps):
+    """The oracle under the batch's stopping rule: test every K steps; stop at the first
+    criterion firing, the first shared component of the two nuclei, or max_steps."""
+    o = OracleSim(s.q, s.nx, s.ny, 1, s.tau, s.G, s.rho_l, s.rho_g, s.amp, s.seed, s.theta, s.K,
+                  s.film_max)
+    o.seed_nuclei(s.centres, s.radii, s.budgets, 0.0)
+    if o.topo_events():
+        return o, -1, 0, 0
+    while o.t < max_steps:
+        o.step(min(s.K, max_steps - o.t))
+        ev, te = o.events(), o.topo_events()
+        if ev or te:
+            break
+    ev, te = o.events(), o.topo_events()
+    return o, (ev[0]["step"] if ev else -1), (te[0]["step"] if te else -1), o.t
+
+
+def small_batch(n, seed=11, lo=64, hi=96, max_steps=300):
+    return W.batch(n=n, seed=seed, lo=lo, hi=hi, max_steps=max_steps)
+
+
+def test_batch_small_runs_and_is_repeatable():
+    spec = small_batch(8, max_steps=40)
+    print("[gpu] batch 8 boxes, 40 steps", flush=True)
+    b = sc.Batch(spec)
+    r1, ms1 = b.run()
+    r2, ms2 = b.run()
+    assert r1 == r2
+    for r in r1:
+        assert r["status"] == 0 and 0 < r["steps_run"] <= 40
+
+
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_batch_density_matches_oracle_after_fixed_steps(compute):
+    """Without stopping events the boxes run exactly max_steps; compare every node."""
+    spec = small_batch(6, seed=3, max_steps=100)
+    spec.K = 1000  # no test pass inside the horizon: a pure 100-step comparison
+    print(f"[gpu] batch 6 boxes, 100 steps, compute {compute}", flush=True)
+    b = sc.Batch(spec, compute=compute)
+    res, _ = b.run()
+    tol = 1e-5 if compute == "f64" else 1e-4
+    for k in range(spec.n):
+        s = spec.instance(k)
+        assert res[k]["steps_run"] == 100
+        o = OracleSim(9, s.nx, s.ny, 1, s.tau, s.G, s.rho_l, s.rho_g, s.amp, s.seed, 0.0, 0, 8)
+        o.seed_nuclei(s.centres, s.radii, s.budgets, 0.0)
+        o.step(100)
+        ro, _, to = o.fields()
+        rg = b.density(k).astype(np.float64)
+        err = np.max(np.abs(rg - ro) / ro)
+        print(f"box {k} {s.nx}x{s.ny} G {s.G:.3f}: rho err {err:.2e}")
+        assert err <= tol
+
+
+def test_batch_merge_steps_match_oracle_sample():
+    """Merge (criterion) and topological steps of sampled boxes under the stopping rule."""
+    spec = small_batch(24, seed=5, lo=64, hi=112, max_steps=400)
+    print("[gpu] batch 24 boxes, up to 400 steps, merge steps vs oracle", flush=True)
+    b = sc.Batch(spec)
+    res, ms = b.run()
+    mism = []
+    for k in range(spec.n):
+        s = spec.instance(k)
+        _, m, tp, t = oracle_run(s, spec.max_steps)
+        g = res[k]
+        print(f"box {k} {s.nx}x{s.ny} R {s.radii[0]:.0f} gap {spec.gap[k]} G {s.G:.3f}: "
+              f"gpu merge {g['merge_step']} topo {g['topo_step']} run {g['steps_run']} | "
+              f"oracle merge {m} topo {tp} run {t}")
+        if (g["merge_step"], g["topo_step"], g["steps_run"]) != (m, tp, t):
+            mism.append(k)
+    assert not mism, mism

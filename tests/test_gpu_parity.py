@@ -276,3 +276,35 @@ def test_invalid_seed_arguments():
     with pytest.raises(sc.ScError):
         g.seed_nuclei(np.zeros((1, 3)), np.array([2.0]), np.array([1.0]), float("nan"))
     g.step(3)  # the handle is still usable
+
+
+# ---- tiling is invisible: every tile and variant gives the same bits; tuning keeps the state ------
+@pytest.mark.parametrize("q,shape", [(9, (150, 90, 1)), (19, (70, 40, 30))])
+def test_tiles_variants_bitwise_equal_and_autotune_keeps_state(q, shape):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(4)
+    centres = np.stack([rng.integers(0, nx, 3), rng.integers(0, ny, 3),
+                        rng.integers(0, nz, 3) if q == 19 else np.zeros(3)], axis=1).astype(float)
+    spec = W.SimSpec(name="tiles", q=q, nx=nx, ny=ny, nz=nz, tau=0.9, K=10, centres=centres,
+                     radii=np.full(3, 7.0), budgets=np.full(3, 1e-2), rate=1e-4)
+    shapes = ([(64, 1, 3, 1), (128, 1, 8, 1), (256, 1, 64, 1)] if q == 9 else
+              [(32, 4, 5, 1), (64, 8, 16, 1), (32, 8, 7, 2), (16, 16, 64, 2)])
+    ref = None
+    for tx, ty, tz, v in shapes:
+        g = gpu_from_spec(spec, tile=(tx, ty, tz), variant=v)
+        g.step(30)
+        f = g.get_populations()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), (tx, ty, tz, v)
+        g.close()
+    g = gpu_from_spec(spec)
+    g.step(30)
+    before = g.get_populations()
+    table = g.autotune(trials=2)
+    assert len(table) > 0 and all(e["us"] > 0 for e in table)
+    assert np.array_equal(g.get_populations(), before)
+    g.step(5)
+    h = gpu_from_spec(spec, tile=shapes[0][:3], variant=shapes[0][3])
+    h.step(35)
+    assert np.array_equal(g.get_populations(), h.get_populations())

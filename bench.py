@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("foam_3d", "foam_2d", "two_bubble", "foam_3d_large")
+WORKLOADS = ("foam_3d", "foam_2d", "two_bubble", "foam_3d_large", "batch")
 
 
 def parse():
@@ -36,13 +36,17 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
     ap.add_argument("--compute", default="auto", choices=("auto", "f32", "f64"))
     ap.add_argument("--tile", default=None, help="tx,ty,tz[,variant] of the step kernel")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the step-kernel autotuner (default shape or --tile)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the step-kernel autotuner before timing (default: the shape "
+                         "stored by paper_1708_01608_amd.tune, else the built-in default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0,
                     help="oracle steps timed for cpu_baseline (0: pick ~10-30 s)")
     ap.add_argument("--variants", action="store_true",
                     help="also time FP32-compute / 16-bit storage variants (extra JSON lines)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="also run a plain device copy of BYTES bytes (calibrates the HBM "
+                         "counters of a profiler run against a kernel of known traffic)")
     return ap.parse_args()
 
 
@@ -59,21 +63,21 @@ def bytes_per_node(q, storage):
 
 def step_kernel_hash():
     h = hashlib.sha256()
-    for f in ("sc_step.hip", "sc_device.hpp"):
+    for f in ("sc_step.hip", "sc_stepcore.hpp", "sc_device.hpp"):
         with open(os.path.join(ROOT, "paper_1708_01608_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, storage, compute, launches_bytes):
+def traffic_from_profile(workload, storage, compute, tile):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current step kernel; else None."""
+    the current step kernel source with the same tile; else None."""
     path = os.path.join(ROOT, "profiles", f"step_counters_{workload}_{storage}_{compute}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_hash") != step_kernel_hash():
+    if d.get("kernel_hash") != step_kernel_hash() or list(d.get("tile", [])) != list(tile):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -88,7 +92,7 @@ def run_gpu(spec, args, storage, compute, steps, warmup, tile=None):
         tile, variant = tile[:3], tile[3]
     sim = sc.Sim.from_spec(spec, storage=storage, compute=compute, tile=tile, variant=variant)
     sim.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
-    if tile is None and not args.no_autotune:
+    if tile is None and args.autotune:
         sim.autotune(trials=3)
     K = spec.K
     for _ in range(warmup):
@@ -131,6 +135,74 @@ def cpu_baseline(spec, sample_steps):
                        f"(FP64 collide-stream + source; test passes off), {dt:.1f} s")
 
 
+def run_batch(args):
+    """The batching pattern: every box of the batch workload in one persistent launch; one bench
+    step = the whole job (every box to its merge, topological merge or max_steps)."""
+    import torch
+
+    from paper_1708_01608_amd import sc
+    from paper_1708_01608_amd import workloads as W
+
+    spec = W.batch()
+    compute = "f64" if args.compute == "auto" else args.compute
+    b = sc.Batch(spec, compute=compute)
+    for _ in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = 0.0
+    for _ in range(args.steps):
+        res, ms = b.run()
+        kms += ms
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    node_steps = sum(int(spec.nx[k]) * int(spec.ny[k]) * res[k]["steps_run"] for k in range(spec.n))
+    mlups = node_steps * args.steps / wall / 1e6
+    achieved = 72.0 * node_steps / (kms / args.steps / 1e3) / 1e9
+    merged = sum(1 for r in res if r["merge_step"] >= 0)
+    topo = sum(1 for r in res if r["topo_step"] >= 0 and r["merge_step"] < 0)
+    b.close()
+    # the same kind of boxes one at a time through the single-box API (sampled)
+    sample = list(range(0, spec.n, max(1, spec.n // 32)))[:32]
+    t1 = time.perf_counter()
+    ns1 = 0
+    for k in sample:
+        s = spec.instance(k)
+        g = sc.Sim.from_spec(s, compute=compute)
+        g.seed_nuclei(s.centres, s.radii, s.budgets, 0.0)
+        while g.t < spec.max_steps and not g.merge_events() and not g.topo_events():
+            g.step(spec.K)
+        ns1 += s.N * g.t
+        g.close()
+    one_by_one = ns1 / (time.perf_counter() - t1) / 1e6
+    out = {
+        "metric": "Shan-Chen MLUPS & % of HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": compute,
+        "data": "synthetic",
+        "config": {"workload": "batch", "lattice": "D2Q9", "boxes": spec.n,
+                   "nodes": int((spec.nx * spec.ny).sum()), "node_steps": node_steps,
+                   "max_steps": spec.max_steps, "test_every": spec.K, "storage": "f32",
+                   "compute": compute, "merged_by_criterion": merged,
+                   "merged_topologically_first": topo},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_batch", "bytes_per_node_step": 72,
+                     "kernel_ms": round(kms / args.steps, 3)},
+        "one_by_one_MLUPS": round(one_by_one, 1),
+        "one_by_one_sample": f"{len(sample)} boxes through sc_create/sc_step",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -144,6 +216,9 @@ def main():
         import __graft_entry__
 
         __graft_entry__.build()
+    if args.workload == "batch":
+        run_batch(args)
+        return
     spec = workload_spec(args.workload)
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     r = run_gpu(spec, args, args.storage, args.compute, args.steps, args.warmup, tile)
@@ -153,7 +228,7 @@ def main():
     bytes_per_launch = bpn * spec.N
     avg_s = r["step_ms"] / 1e3 / max(r["launches"], 1)
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = traffic_from_profile(args.workload, args.storage, r["compute"], bytes_per_launch)
+    traffic = traffic_from_profile(args.workload, args.storage, r["compute"], r["tile"])
     out = {
         "metric": "Shan-Chen MLUPS & % of HBM roofline",
         "value": round(mlups, 1),
@@ -180,7 +255,8 @@ def main():
             "test_every": spec.K,
             "lattice_steps_per_step": spec.K,
             "step_tile": list(r["tile"]),
-            "autotuned": args.tile is None and not args.no_autotune,
+            "shape_source": ("--tile" if args.tile else "autotune" if args.autotune
+                             else "tuned_shapes.json or default"),
         },
         "roofline": {
             "bound": "hbm",
@@ -201,9 +277,26 @@ def main():
             "wall": round(r["wall"] * 1e3, 3),
         },
     }
+    copy_gbs, read_gbs = sc.hbm_probe(min(bytes_per_launch // 2, 2550136832), 5)
+    out["roofline"]["measured_copy_GBps"] = round(copy_gbs, 1)
+    out["roofline"]["measured_read_GBps"] = round(read_gbs, 1)
+    out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
+    if args.copy_probe > 0:
+        import torch
+
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_probe_bytes": args.copy_probe,
+                          "copy_GBps": round(2 * args.copy_probe / dt / 1e9, 1)}), flush=True)
     if args.variants:
         for storage, compute in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
             rv = run_gpu(spec, args, storage, compute, args.steps, args.warmup, tile)

@@ -81,7 +81,8 @@ typedef struct sc_params {
     void* stream;              /* hipStream_t to run on; NULL: the library creates one */
     const sc_allocator* allocator; /* NULL: hipMalloc / hipFree */
     int32_t tile_x, tile_y, tile_z; /* step-kernel tile; 0 selects the tuned default */
-    int32_t step_variant;      /* 0 default, 1 plain marching, 2 software-pipelined (D3Q19) */
+    int32_t step_variant;      /* 0 default, 1 plain marching, 2 software-pipelined (D3Q19),
+                                  3 plain with non-temporal population stores */
 } sc_params;
 
 /* One firing of the merge criterion (Sec. 3.1 eta_m: 1 -> 0; Sec. 4 film rupture). */
@@ -244,6 +245,11 @@ int sc_batch_run(struct sc_batch* b, sc_batch_result* results, double* kernel_ms
 /* FP32 density of box k after the last run (FP64 sums of the stored populations). */
 int sc_batch_fields(struct sc_batch* b, int32_t k, float* rho);
 int sc_batch_destroy(struct sc_batch* b);
+
+/* HBM bandwidth probe: best-of-reps GB/s of a float4 copy (read + write) and of a float4
+ * read-only pass over `bytes` (>= 1 MiB) of freshly allocated device memory; the measured
+ * ceiling that the step kernel's bandwidth is compared with.  Uses the null stream. */
+int sc_hbm_probe(size_t bytes, int32_t reps, double* copy_GBps, double* read_GBps);
 
 typedef struct sc_sim sc_sim;
 typedef struct sc_batch sc_batch;

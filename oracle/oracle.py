@@ -146,8 +146,9 @@ class OracleSim:
 
     def seed_nuclei(self, centres, radii, budgets, rate):
         c = np.zeros((len(radii), 3), dtype=np.float64)
-        cc = np.asarray(centres, dtype=np.float64).reshape(len(radii), -1)
-        c[:, : cc.shape[1]] = cc
+        if len(radii) > 0:
+            cc = np.asarray(centres, dtype=np.float64).reshape(len(radii), -1)
+            c[:, : cc.shape[1]] = cc
         r = np.ascontiguousarray(radii, dtype=np.float64)
         b = np.ascontiguousarray(budgets, dtype=np.float64)
         rc = self._lib.orc_seed_nuclei(self._h, len(r), _ptr(c), _ptr(r), _ptr(b), float(rate))

@@ -214,12 +214,13 @@ std::vector<StepShape> tune_candidates(int q)
     std::vector<StepShape> c;
     if (q == SC_D2Q9) {
         for (int tx : {64, 128, 256, 512})
-            for (int tz : {2, 4, 8, 16, 32, 64}) c.push_back(StepShape{tx, 1, tz, 1});
+            for (int tz : {2, 4, 8, 16, 32, 64})
+                for (int v : {1, 3}) c.push_back(StepShape{tx, 1, tz, v});
     } else {
-        const int tiles[][2] = {{32, 4}, {32, 8}, {32, 16}, {64, 4}, {64, 8}, {128, 4}, {16, 16}};
+        const int tiles[][2] = {{32, 8}, {64, 4}, {64, 8}, {128, 4}, {128, 8}, {256, 4}};
         for (auto& t : tiles)
-            for (int tz : {8, 16, 32, 64})
-                for (int v : {1, 2}) c.push_back(StepShape{t[0], t[1], tz, v});
+            for (int tz : {16, 32, 64})
+                for (int v : {1, 2, 3}) c.push_back(StepShape{t[0], t[1], tz, v});
     }
     return c;
 }

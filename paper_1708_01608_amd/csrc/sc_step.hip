@@ -43,7 +43,7 @@ __device__ __forceinline__ int logical_block(const StepGrid& g)
 // ------------------------------------------------------------------------------------------
 // D2Q9: a block owns TX nodes of a row and marches `planes` rows in y.
 // ------------------------------------------------------------------------------------------
-template <typename S, typename A, int TX>
+template <typename S, typename A, int TX, bool NT = false>
 __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __restrict__ dst,
                                                StepArgs a, StepGrid grid)
 {
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
                 if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
             }
             const A gp = -c.G * pc;
-            collide_store<9, A, S>(dst, N, x + nx * y, cur, dcur, gp * fx, gp * fy, (A)0, c);
+            collide_store<9, A, S, NT>(dst, N, x + nx * y, cur, dcur, gp * fx, gp * fy, (A)0, c);
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) cur[i] = nxt[i];
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
 // ------------------------------------------------------------------------------------------
 // D3Q19: a block owns a TX x TY tile of an x-y plane and marches `planes` planes in z.
 // ------------------------------------------------------------------------------------------
-template <typename S, typename A, int TX, int TY>
+template <typename S, typename A, int TX, int TY, bool NT = false>
 __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S* __restrict__ dst,
                                                    StepArgs a, StepGrid grid)
 {
@@ -244,8 +244,8 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
                 if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
             }
             const A gp = -c.G * pc;
-            collide_store<19, A, S>(dst, N, x + nx * (y + ny * z), cur, dcur, gp * fx, gp * fy,
-                                    gp * fz, c);
+            collide_store<19, A, S, NT>(dst, N, x + nx * (y + ny * z), cur, dcur, gp * fx,
+                                        gp * fy, gp * fz, c);
         }
 #pragma unroll
         for (int i = 0; i < 19; ++i) cur[i] = nxt[i];
@@ -383,14 +383,15 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
 bool step_shape_supported(int q, const StepShape& s)
 {
     if (s.tile_z < 1) return false;
-    if (s.variant < 0 || s.variant > 2 || (q == 9 && s.variant == 2)) return false;
+    if (s.variant < 1 || s.variant > 3 || (q == 9 && s.variant == 2)) return false;
     if (q == 9) return s.tile_y == 1 && (s.tile_x == 64 || s.tile_x == 128 || s.tile_x == 256 ||
                                           s.tile_x == 512);
     if (q == 19) {
         const int tx = s.tile_x, ty = s.tile_y;
         const bool known = (tx == 32 && (ty == 4 || ty == 8 || ty == 16)) ||
-                           (tx == 64 && (ty == 4 || ty == 8)) || (tx == 128 && ty == 4) ||
-                           (tx == 16 && ty == 16);
+                           (tx == 64 && (ty == 4 || ty == 8)) ||
+                           (tx == 128 && (ty == 4 || ty == 8)) ||
+                           (tx == 256 && ty == 4) || (tx == 16 && ty == 16);
         return known && 2 * (tx + 2) + 2 * ty <= tx * ty;
     }
     return false;
@@ -415,13 +416,20 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
     dim3 grid(nb);
 #define SC_L2(TX)                                                                                \
     if (s.tile_x == TX) {                                                                        \
-        hipLaunchKernelGGL((k_step2d<S, A, TX>), grid, dim3(TX), 0, st, src, dst, a, g);         \
+        if (s.variant == 3)                                                                      \
+            hipLaunchKernelGGL((k_step2d<S, A, TX, true>), grid, dim3(TX), 0, st, src, dst, a,   \
+                               g);                                                               \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_step2d<S, A, TX>), grid, dim3(TX), 0, st, src, dst, a, g);     \
         return hipGetLastError();                                                                \
     }
 #define SC_L3(TX, TY)                                                                            \
     if (s.tile_x == TX && s.tile_y == TY) {                                                      \
         if (s.variant == 2)                                                                      \
             hipLaunchKernelGGL((k_step3d_pipe<S, A, TX, TY>), grid, dim3(TX * TY), 0, st, src,   \
+                               dst, a, g);                                                       \
+        else if (s.variant == 3)                                                                 \
+            hipLaunchKernelGGL((k_step3d<S, A, TX, TY, true>), grid, dim3(TX * TY), 0, st, src,  \
                                dst, a, g);                                                       \
         else                                                                                     \
             hipLaunchKernelGGL((k_step3d<S, A, TX, TY>), grid, dim3(TX * TY), 0, st, src, dst,   \
@@ -432,7 +440,7 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
         SC_L2(64) SC_L2(128) SC_L2(256) SC_L2(512)
     } else {
         SC_L3(32, 4) SC_L3(32, 8) SC_L3(32, 16) SC_L3(64, 4) SC_L3(64, 8) SC_L3(128, 4)
-        SC_L3(16, 16)
+        SC_L3(16, 16) SC_L3(128, 8) SC_L3(256, 4)
     }
 #undef SC_L2
 #undef SC_L3

@@ -13,13 +13,18 @@ __device__ __forceinline__ void pull_node(const S* __restrict__ src, int64_t N, 
                                           int zm, int zp, float* g)
 {
     using L = lat<Q>;
+    // unsigned 32-bit byte offsets from a per-direction base: one add per load, and the base
+    // stays in scalar registers (the byte offset of any node is < 4 N < 2^32)
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t xo[3] = {(uint32_t)xp, (uint32_t)x, (uint32_t)xm};   // by -e_x: +1 -> xm
+    const uint32_t yo[3] = {(uint32_t)yp * nx, (uint32_t)y * nx, (uint32_t)ym * nx};
+    const uint32_t zo[3] = {(uint32_t)zp * plane, (uint32_t)z * plane, (uint32_t)zm * plane};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int sx = L::ex[i] > 0 ? xm : (L::ex[i] < 0 ? xp : x);
-        const int sy = L::ey[i] > 0 ? ym : (L::ey[i] < 0 ? yp : y);
-        const int sz = L::ez[i] > 0 ? zm : (L::ez[i] < 0 ? zp : z);
-        const S* base = src + (int64_t)i * N;
-        g[i] = load_f(base[sx + nx * (sy + ny * sz)]);
+        const uint32_t off = (xo[L::ex[i] + 1] + yo[L::ey[i] + 1] + zo[L::ez[i] + 1]) *
+                             (uint32_t)sizeof(S);
+        const char* base = reinterpret_cast<const char*>(src + (int64_t)i * N);
+        g[i] = load_f(*reinterpret_cast<const S*>(base + off));
     }
 }
 
@@ -54,7 +59,20 @@ __device__ __forceinline__ Coef<double> coef_of(const StepArgs& a, double)
 //   P_i = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2,
 // becomes g_i* = g_i + omega (w_i rho P_i - h_i): every intermediate is small, so rounding
 // happens at the scale of the non-equilibrium part instead of w_i rho.
-template <int Q, typename A, typename S>
+// Store of one post-collision population; NT = non-temporal (streaming) store of FP32 values,
+// which are not read again before the next step, so they need not displace loads from L2.
+template <bool NT, typename S>
+__device__ __forceinline__ void put(S* p, S v)
+{
+    *p = v;
+}
+template <>
+__device__ __forceinline__ void put<true, float>(float* p, float v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+template <int Q, typename A, typename S, bool NT = false>
 __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, int idx,
                                               const float* g, A drho, A Fx, A Fy, A Fz,
                                               const Coef<A>& c)
@@ -83,7 +101,7 @@ __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, in
         const A h = fmad(-w, drho, gi);
         const A d = fmad(w * rho, P, -h);
         const A gs = fmad(c.omega, d, gi);
-        dst[(int64_t)i * N + idx] = store_f<S>((float)gs);
+        put<NT, S>(dst + (int64_t)i * N + idx, store_f<S>((float)gs));
     }
 }
 

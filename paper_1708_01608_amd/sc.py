@@ -98,6 +98,7 @@ EXPORTS = (
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
+    "sc_hbm_probe",
 )
 
 _lib = None
@@ -150,6 +151,7 @@ def load_library(path=LIB_PATH):
         "sc_batch_fields": (C.c_int, [P, C.c_int32, P]),
         "sc_batch_destroy": (C.c_int, [P]),
         "sc_autotune": (C.c_int, [P, C.c_int32, P, C.c_int32, P]),
+        "sc_hbm_probe": (C.c_int, [C.c_size_t, C.c_int32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -167,6 +169,14 @@ def _check(rc):
     if rc != SC_OK:
         msg = load_library().sc_last_error()
         raise ScError(rc, msg.decode() if msg else "")
+
+
+def hbm_probe(nbytes=2550136832, reps=5):
+    """(copy GB/s, read GB/s) of the library's float4 probe kernels."""
+    lib = load_library()
+    c, r = C.c_double(), C.c_double()
+    _check(lib.sc_hbm_probe(int(nbytes), int(reps), C.byref(c), C.byref(r)))
+    return c.value, r.value
 
 
 def lattice(q):
@@ -202,12 +212,26 @@ class TorchMemory:
         self.struct = Allocator(self._alloc, self._free, None)
 
 
+def _tuned_shape(q, nx, ny, nz, storage, compute, variant):
+    """Step-kernel shape stored by paper_1708_01608_amd.tune for this box, if any."""
+    from . import tune
+
+    st = storage if isinstance(storage, str) else {0: "f32", 1: "f16", 2: "bf16"}[storage]
+    comp = compute
+    if comp == "auto":
+        comp = "f64" if st == "f32" else "f32"
+    e = tune.load().get(tune.key(q, nx, ny, nz, st, comp))
+    if not e:
+        return None, variant
+    return tuple(e["tile"]), e["variant"]
+
+
 class Sim:
     """One periodic Shan-Chen box on the GPU (a handle of libsc)."""
 
     def __init__(self, q=9, nx=128, ny=128, nz=1, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16,
                  amp=1e-3, seed=1, theta=0.0, K=10, film_max=8, storage="f32", compute="auto",
-                 rho_ref=-1.0, tile=None, variant=0, memory="torch"):
+                 rho_ref=-1.0, tile=None, variant=0, memory="torch", tuned=True):
         self._lib = load_library()
         self._h = None
         p = Params()
@@ -219,6 +243,9 @@ class Sim:
         p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         p.compute = COMPUTE[compute] if isinstance(compute, str) else int(compute)
         p.rho_ref = rho_ref
+        comp_name = compute if isinstance(compute, str) else {0: "auto", 1: "f32", 2: "f64"}[compute]
+        if tile is None and tuned:
+            tile, variant = _tuned_shape(q, nx, ny, nz, storage, comp_name, variant)
         if tile is not None:
             p.tile_x, p.tile_y, p.tile_z = tile
         p.step_variant = int(variant)
@@ -255,8 +282,9 @@ class Sim:
     def seed_nuclei(self, centres, radii, budgets, rate):
         n = len(radii)
         c = np.zeros((n, 3))
-        cc = np.asarray(centres, dtype=np.float64).reshape(n, -1)
-        c[:, : cc.shape[1]] = cc
+        if n > 0:
+            cc = np.asarray(centres, dtype=np.float64).reshape(n, -1)
+            c[:, : cc.shape[1]] = cc
         r = np.ascontiguousarray(radii, dtype=np.float64)
         b = np.ascontiguousarray(budgets, dtype=np.float64)
         _check(self._lib.sc_seed_nuclei(self._h, n, _ptr(c), _ptr(r), _ptr(b), float(rate)))

@@ -146,6 +146,7 @@ def run_batch(args):
     spec = W.batch()
     compute = "f64" if args.compute == "auto" else args.compute
     b = sc.Batch(spec, compute=compute)
+    rows_per_thread, tune_ms = b.tune(trial_steps=50)
     for _ in range(args.warmup):
         b.run()
     torch.cuda.synchronize()
@@ -191,7 +192,9 @@ def run_batch(args):
         "config": {"workload": "batch", "lattice": "D2Q9", "boxes": spec.n,
                    "nodes": int((spec.nx * spec.ny).sum()), "node_steps": node_steps,
                    "max_steps": spec.max_steps, "test_every": spec.K, "storage": "f32",
-                   "compute": compute, "merged_by_criterion": merged,
+                   "compute": compute, "rows_per_thread": rows_per_thread,
+                   "tune_ms_rb124": [round(v, 2) for v in tune_ms],
+                   "merged_by_criterion": merged,
                    "merged_topologically_first": topo},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

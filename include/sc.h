@@ -65,7 +65,9 @@ typedef struct sc_allocator {
 typedef struct sc_params {
     uint32_t abi_version;      /* must equal SC_ABI_VERSION */
     int32_t lattice;           /* SC_D2Q9 or SC_D3Q19 */
-    int32_t nx, ny, nz;        /* periodic box; nz == 1 for D2Q9 */
+    int32_t nx, ny, nz;        /* periodic box; nz == 1 for D2Q9; nx ny nz times the bytes of
+                                  one stored value (4 for F32, 2 for F16/BF16) must be <= 2^32
+                                  (e.g. 1024^3 on F32): kernels use 32-bit byte offsets */
     double tau;                /* BGK relaxation time, > 0.5 */
     double G;                  /* Shan-Chen strength (Sec. 3.1); G < 0 attracts */
     double rho_liquid;         /* fill density of every node (Sec. 3.1 "liquid") */
@@ -242,6 +244,10 @@ int sc_batch_create(int32_t n, const sc_batch_instance* inst, int32_t test_every
 /* Runs every box from its initial state (repeatable); results[n] may be NULL; *kernel_ms gets
  * the HIP-event time of the launch.  Synchronous. */
 int sc_batch_run(struct sc_batch* b, sc_batch_result* results, double* kernel_ms);
+/* Autotuner of the batch: runs every box for trial_steps with each candidate number of rows a
+ * thread carries per iteration of the box step (1, 2, 4), keeps the fastest.  ms[3] (may be
+ * NULL) receives the three timings.  The next sc_batch_run starts from the initial state. */
+int sc_batch_tune(struct sc_batch* b, int32_t trial_steps, int32_t* rows_per_thread, double* ms);
 /* FP32 density of box k after the last run (FP64 sums of the stored populations). */
 int sc_batch_fields(struct sc_batch* b, int32_t k, float* rho);
 int sc_batch_destroy(struct sc_batch* b);

@@ -626,6 +626,9 @@ int validate(const sc_params* p)
     if (p->test_every < 0) return fail(SC_E_INVAL, "test_every must be >= 0");
     if (p->film_max < 1) return fail(SC_E_INVAL, "film_max must be >= 1");
     if (p->storage < SC_STORE_F32 || p->storage > SC_STORE_BF16) return fail(SC_E_INVAL, "unknown storage");
+    // the step kernels address a population array with 32-bit byte offsets
+    if (N * (double)storage_bytes(p->storage) > 4294967296.0)
+        return fail(SC_E_INVAL, "box too large: nodes x bytes per stored value must be <= 2^32");
     if (p->compute < SC_COMPUTE_AUTO || p->compute > SC_COMPUTE_F64) return fail(SC_E_INVAL, "unknown compute type");
     if (p->compute == SC_COMPUTE_F64 && p->storage != SC_STORE_F32)
         return fail(SC_E_UNSUPPORTED, "FP64 arithmetic is offered on FP32 storage only");

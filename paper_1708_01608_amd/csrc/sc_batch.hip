@@ -100,55 +100,92 @@ __device__ void batch_init(float* f, const BatchInst& in)
     }
 }
 
-// ---- one time step of a whole box --------------------------------------------------------------
-template <typename A>
+// ---- one time step of a whole box ------------------------------------------------------------
+// The nodes of a box are walked in blocks of rb = max(1, 256 RB / nx) rows: a block has
+// rb * nx <= 256 RB node slots j = t + 256 r (r < RB), slot j holding column j % nx of the
+// block's row j / nx, so narrow boxes keep every lane busy.  Blocks are numbered virtually:
+// block b holds rows w = (b - 1) rb + j / nx (row w mod ny of the box), so block 0 is the
+// prologue (the rb rows before row 0) and blocks past the end wrap to the first rows.  psi of
+// block b lives in LDS ring slot b mod 4.  Iteration b (1 <= b <= nblk) loads block b + 1 and
+// collides block b; its one barrier separates the writes of slot (b+1) mod 4 from the reads of
+// block b - 3, done in iteration b - 2.
+template <typename A, int RB>
 __device__ void batch_step(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny,
-                           const Coef<A>& c, A (*ps)[kBatchThreads])
+                           const Coef<A>& c, A* __restrict__ ps)
 {
     using L = lat<9>;
+    constexpr int W = kBatchThreads * RB;  // node slots per block (and LDS entries per ring slot)
     const int N = nx * ny;
+    const int rb = max(1, W / nx);
+    const int nblk = (ny + rb - 1) / rb;
     const int t = threadIdx.x;
-    const bool own = t < nx;
-    const int x = own ? t : 0;
-    const int xm = wrap_once(x - 1, nx), xp = wrap_once(x + 1, nx);
-    float cur[9], nxt[9];
-    A dcur = (A)0, dnxt = (A)0;
-    if (own) {
-        float g[9];
-        const int y = ny - 1;
-        pull_node<9>(src, N, nx, ny, x, xm, xp, y, y - 1, 0, 0, 0, 0, g);
-        ps[0][x] = psi_f(c.rho_ref + sum_dev<9, A>(g));
-        pull_node<9>(src, N, nx, ny, x, xm, xp, 0, ny - 1, 1, 0, 0, 0, cur);
-        dcur = sum_dev<9, A>(cur);
-        ps[1][x] = psi_f(c.rho_ref + dcur);
+    int col[RB], row[RB], xm[RB], xp[RB];
+    bool act[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int j = t + kBatchThreads * r;
+        row[r] = j / nx;
+        col[r] = j - row[r] * nx;
+        act[r] = row[r] < rb;
+        xm[r] = wrap_once(col[r] - 1, nx);
+        xp[r] = wrap_once(col[r] + 1, nx);
     }
-    for (int y = 0; y < ny; ++y) {
-        const int s = (y + 1) & 3, sn = (s + 1) & 3, sp = (s + 3) & 3;
-        if (own) {
-            const int yn = wrap_once(y + 1, ny);
-            pull_node<9>(src, N, nx, ny, x, xm, xp, yn, wrap_once(yn - 1, ny),
-                         wrap_once(yn + 1, ny), 0, 0, 0, nxt);
-            dnxt = sum_dev<9, A>(nxt);
-            ps[sn][x] = psi_f(c.rho_ref + dnxt);
+    float cur[RB][9], nxt[RB][9];
+    A dcur[RB], dnxt[RB];
+    // populations (kept) and psi (into LDS) of block b's slot r
+    auto load = [&](int blk, int r, float* g) -> A {
+        int y = ((blk - 1) * rb + row[r]) % ny;
+        if (y < 0) y += ny;
+        pull_node<9>(src, N, nx, ny, col[r], xm[r], xp[r], y, wrap_once(y - 1, ny),
+                        wrap_once(y + 1, ny), 0, 0, 0, g);
+        const A d = sum_dev<9, A>(g);
+        ps[(blk & 3) * W + t + kBatchThreads * r] = psi_f(c.rho_ref + d);
+        return d;
+    };
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        if (act[r]) {
+            float g[9];
+            (void)load(0, r, g);
+            dcur[r] = load(1, r, cur[r]);
         }
+    }
+    for (int blk = 1; blk <= nblk; ++blk) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (act[r]) dnxt[r] = load(blk + 1, r, nxt[r]);
         __syncthreads();
-        if (own) {
-            const A pc = ps[s][x];
-            A fx = (A)0, fy = (A)0;
+        const int sb = (blk & 3) * W, sn = ((blk + 1) & 3) * W, sp = ((blk + 3) & 3) * W;
 #pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const int slot = L::ey[i] > 0 ? sn : (L::ey[i] < 0 ? sp : s);
-                const int xx = L::ex[i] > 0 ? xp : (L::ex[i] < 0 ? xm : x);
-                const A pn = weight<9, A>(i) * ps[slot][xx];
-                if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
-                if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
+        for (int r = 0; r < RB; ++r) {
+            const int y = (blk - 1) * rb + row[r];
+            if (act[r] && y < ny) {
+                // row starts of rows y - 1, y, y + 1 in the ring
+                const int j0 = t + kBatchThreads * r - col[r];
+                const int rc = sb + j0;
+                const int ru = row[r] + 1 < rb ? rc + nx : sn;
+                const int rd = row[r] > 0 ? rc - nx : sp + (rb - 1) * nx;
+                const A pc = ps[rc + col[r]];
+                A fx = (A)0, fy = (A)0;  // same order as the single-box kernel
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    const int rw = L::ey[i] > 0 ? ru : (L::ey[i] < 0 ? rd : rc);
+                    const int xx = L::ex[i] > 0 ? xp[r] : (L::ex[i] < 0 ? xm[r] : col[r]);
+                    const A pn = weight<9, A>(i) * ps[rw + xx];
+                    if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
+                    if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
+                }
+                const A gp = -c.G * pc;
+                collide_store<9, A, float>(dst, N, (uint32_t)(col[r] + nx * y), cur[r], dcur[r],
+                                           gp * fx, gp * fy, (A)0, c);
             }
-            const A gp = -c.G * pc;
-            collide_store<9, A, float>(dst, N, x + nx * y, cur, dcur, gp * fx, gp * fy, (A)0, c);
         }
 #pragma unroll
-        for (int i = 0; i < 9; ++i) cur[i] = nxt[i];
-        dcur = dnxt;
+        for (int r = 0; r < RB; ++r) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) cur[r][i] = nxt[r][i];
+            dcur[r] = dnxt[r];
+        }
     }
     __syncthreads();  // this step's stores are the next step's loads
 }
@@ -192,10 +229,11 @@ __device__ __forceinline__ double rho64(const float* f, int N, int nx, int ny, i
     return s;
 }
 
-__device__ __forceinline__ int64_t min_img_i(int64_t d, int n)
+// minimal-image offset of d in (-n, n) on a ring of n nodes (boxes are small: 32-bit is exact)
+__device__ __forceinline__ int min_img_i(int d, int n)
 {
-    const int64_t h = n / 2;
-    int64_t r = (d + h) % n;
+    const int h = n / 2;
+    int r = (d + h) % n;
     if (r < 0) r += n;
     return r - h;
 }
@@ -249,18 +287,23 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
     }
     // statistics: counts and integer minimal-image offset sums from each bubble's anchor node,
     // and the FP64 totals of the box
+    // the bubble of nucleus 1 is anchored at nucleus 0 when both share it
+    int ax[2], ay[2];
+    for (int b = 0; b < 2; ++b) {
+        const int a = (b == 1 && comp[1] == comp[0]) ? nd[0] : nd[b];
+        ax[b] = a % nx;
+        ay[b] = a / nx;
+    }
     long long cnt[2] = {0, 0}, sx[2] = {0, 0}, sy[2] = {0, 0};
     double M = 0.0, Jx = 0.0, Jy = 0.0;
     for (int n = t; n < N; n += kBatchThreads) {
         const uint32_t p = par[n];
-        const int x = n % nx, y = n / nx;
+        const int y = n / nx, x = n - y * nx;
         for (int b = 0; b < 2; ++b) {
             if (p == kNone || p != comp[b]) continue;
-            // the bubble of nucleus 1 is anchored at nucleus 0 when both share it
-            const int a = (b == 1 && comp[1] == comp[0]) ? nd[0] : nd[b];
             cnt[b] += 1;
-            sx[b] += min_img_i((int64_t)x - a % nx, nx);
-            sy[b] += min_img_i((int64_t)y - a / nx, ny);
+            sx[b] += min_img_i(x - ax[b], nx);
+            sy[b] += min_img_i(y - ay[b], ny);
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -375,29 +418,35 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
     return stop;
 }
 
-template <typename A>
+template <typename A, int RB>
 __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs b)
 {
-    __shared__ A ps[4][kBatchThreads];
+    __shared__ A ps[4 * RB * kBatchThreads];
     __shared__ Scratch sh;
+    __shared__ BatchOut s_out;
     __shared__ int s_idx;
     for (;;) {
         if (threadIdx.x == 0) s_idx = (int)atomicAdd(b.counter, 1u);
         __syncthreads();
-        const int q = s_idx;
+        // the queue index is uniform over the workgroup: keep it (and the box record loaded
+        // through it) in scalar registers
+        const int q = __builtin_amdgcn_readfirstlane(s_idx);
         __syncthreads();
         if (q >= b.n) return;
-        const int k = b.order[q];
+        const int k = __builtin_amdgcn_readfirstlane(b.order[q]);
         const BatchInst in = b.inst[k];
         const int N = in.nx * in.ny;
         float* f0 = b.pool + in.off;
         float* f1 = f0 + (int64_t)9 * N;
         uint32_t* par = b.lab + in.loff;
         const Coef<A> c{(A)in.tau, (A)(1.0 / in.tau), (A)in.G, (A)0};
-        BatchOut o;
-        o.merge_step = -1; o.topo_step = -1; o.steps_run = 0; o.film_node = -1;
-        o.film_len = 0; o.status = 0; o.lap_p = 0.0; o.rho_film = 0.0;
-        o.totals[0] = o.totals[1] = o.totals[2] = 0.0;
+        // the box's record is written by thread 0 only: keep it in LDS, not in every lane
+        BatchOut& o = s_out;
+        if (threadIdx.x == 0) {
+            o.merge_step = -1; o.topo_step = -1; o.steps_run = 0; o.film_node = -1;
+            o.film_len = 0; o.status = 0; o.lap_p = 0.0; o.rho_film = 0.0;
+            o.totals[0] = o.totals[1] = o.totals[2] = 0.0;
+        }
 
         batch_init(f0, in);
         __syncthreads();
@@ -405,7 +454,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs b)
         int cur = 0;
         int64_t step = 0;
         while (!stop && step < b.max_steps) {
-            batch_step<A>(cur ? f1 : f0, cur ? f0 : f1, in.nx, in.ny, c, ps);
+            batch_step<A, RB>(cur ? f1 : f0, cur ? f0 : f1, in.nx, in.ny, c, ps);
             cur ^= 1;
             ++step;
             if (b.K > 0 && step % b.K == 0)
@@ -439,6 +488,7 @@ using namespace sc;
 struct sc_batch {
     int n = 0;
     int K = 10, film_max = 8, max_steps = 5000, compute = SC_COMPUTE_F64;
+    int rb = 2;  // rows per thread per iteration of the box step
     hipStream_t stream = nullptr;
     bool own_stream = false;
     sc_allocator alloc{};
@@ -486,6 +536,35 @@ void brelease(sc_batch* b)
     for (void* p : {b->d_inst, b->d_out, b->d_order, b->d_pool, b->d_lab, b->d_counter, b->d_rho})
         bfree(b, p);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+}  // namespace
+
+namespace {
+
+hipError_t batch_occupancy(int compute, int rb, int* per_cu)
+{
+#define SC_OCC(A, RB) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<A, RB>, kBatchThreads, 0)
+    if (compute == SC_COMPUTE_F32) {
+        if (rb == 1) SC_OCC(float, 1);
+        if (rb == 2) SC_OCC(float, 2);
+        SC_OCC(float, 4);
+    }
+    if (rb == 1) SC_OCC(double, 1);
+    if (rb == 2) SC_OCC(double, 2);
+    SC_OCC(double, 4);
+#undef SC_OCC
+}
+
+void batch_launch(int compute, int rb, int grid, hipStream_t st, const BatchArgs& a)
+{
+#define SC_LB(A, RB) hipLaunchKernelGGL((k_batch<A, RB>), dim3(grid), dim3(kBatchThreads), 0, st, a)
+    if (compute == SC_COMPUTE_F32) {
+        if (rb == 1) SC_LB(float, 1); else if (rb == 2) SC_LB(float, 2); else SC_LB(float, 4);
+    } else {
+        if (rb == 1) SC_LB(double, 1); else if (rb == 2) SC_LB(double, 2); else SC_LB(double, 4);
+    }
+#undef SC_LB
 }
 
 }  // namespace
@@ -622,17 +701,11 @@ int sc_batch_run(sc_batch* b, sc_batch_result* results, double* kernel_ms)
         a.K = b->K;
         a.film_max = b->film_max;
         a.max_steps = b->max_steps;
-        if (b->compute == SC_COMPUTE_F32)
-            BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float>, kBatchThreads, 0));
-        else
-            BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double>, kBatchThreads, 0));
+        BHIP(batch_occupancy(b->compute, b->rb, &per_cu));
         const int grid = std::max(1, std::min(b->n, std::max(1, per_cu) * std::max(1, cus)));
         BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, b->stream, (unsigned int*)b->d_counter);
-        if (b->compute == SC_COMPUTE_F32)
-            hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBatchThreads), 0, b->stream, a);
-        else
-            hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBatchThreads), 0, b->stream, a);
+        batch_launch(b->compute, b->rb, grid, b->stream, a);
         hipError_t le = hipGetLastError();
         hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
         if (le != hipSuccess) return set_error(SC_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(le));
@@ -668,6 +741,35 @@ int sc_batch_run(sc_batch* b, sc_batch_result* results, double* kernel_ms)
         }
     }
     return SC_OK;
+}
+
+int sc_batch_tune(sc_batch* b, int32_t trial_steps, int32_t* rows_per_thread, double* ms_out)
+{
+    if (!b) return set_error(SC_E_INVAL, "NULL batch handle");
+    if (trial_steps < 1) return set_error(SC_E_INVAL, "trial_steps >= 1");
+    const int keep_steps = b->max_steps;
+    const int keep_rb = b->rb;
+    double best = 1e300;
+    int best_rb = keep_rb;
+    int rc = SC_OK;
+    b->max_steps = trial_steps;
+    for (int rb : {1, 2, 4}) {
+        b->rb = rb;
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        double ms = 0.0;
+        rc = sc_batch_run(b, nullptr, &ms);
+        if (rc != SC_OK) break;
+        if (ms_out) ms_out[rb == 1 ? 0 : rb == 2 ? 1 : 2] = ms;
+        if (ms < best) { best = ms; best_rb = rb; }
+    }
+    b->max_steps = keep_steps;
+    b->rb = rc == SC_OK ? best_rb : keep_rb;
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    b->ran = false;
+    if (rows_per_thread) *rows_per_thread = b->rb;
+    return rc;
 }
 
 int sc_batch_fields(sc_batch* b, int32_t k, float* rho)

@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
                 if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
             }
             const A gp = -c.G * pc;
-            collide_store<9, A, S, NT>(dst, N, x + nx * y, cur, dcur, gp * fx, gp * fy, (A)0, c);
+            collide_store<9, A, S, NT>(dst, N, (uint32_t)(x + nx * y), cur, dcur, gp * fx,
+                                       gp * fy, (A)0, c);
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) cur[i] = nxt[i];
@@ -244,8 +245,8 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
                 if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
             }
             const A gp = -c.G * pc;
-            collide_store<19, A, S, NT>(dst, N, x + nx * (y + ny * z), cur, dcur, gp * fx,
-                                        gp * fy, gp * fz, c);
+            collide_store<19, A, S, NT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
+                                        gp * fx, gp * fy, gp * fz, c);
         }
 #pragma unroll
         for (int i = 0; i < 19; ++i) cur[i] = nxt[i];
@@ -355,8 +356,8 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
                 if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
             }
             const A gp = -c.G * pc;
-            collide_store<19, A, S>(dst, N, x + nx * (y + ny * z), cur, dcur, gp * fx, gp * fy,
-                                    gp * fz, c);
+            collide_store<19, A, S>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
+                                    gp * fx, gp * fy, gp * fz, c);
         }
         A dpre = (A)0;
         if (more) {

@@ -7,14 +7,15 @@
 
 namespace sc {
 
+// Pulled populations g_i = stored_i(x - e_i) of one node: unsigned 32-bit byte offsets from a
+// per-direction base, so one vector add per load and the 64-bit bases stay in scalar registers.
+// The byte offset of any node is below N sizeof(S) <= 2^32 (the library rejects larger boxes).
 template <int Q, typename S>
 __device__ __forceinline__ void pull_node(const S* __restrict__ src, int64_t N, int nx, int ny,
                                           int x, int xm, int xp, int y, int ym, int yp, int z,
                                           int zm, int zp, float* g)
 {
     using L = lat<Q>;
-    // unsigned 32-bit byte offsets from a per-direction base: one add per load, and the base
-    // stays in scalar registers (the byte offset of any node is < 4 N < 2^32)
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t xo[3] = {(uint32_t)xp, (uint32_t)x, (uint32_t)xm};   // by -e_x: +1 -> xm
     const uint32_t yo[3] = {(uint32_t)yp * nx, (uint32_t)y * nx, (uint32_t)ym * nx};
@@ -72,12 +73,29 @@ __device__ __forceinline__ void put<true, float>(float* p, float v)
     __builtin_nontemporal_store(v, p);
 }
 
+// e_i . u with the exactly-zero components left out (a product with 0 would have to be kept
+// under IEEE rules; dropping it changes no value).
+template <int Q, typename A>
+__device__ __forceinline__ A e_dot(int i, A ux, A uy, A uz)
+{
+    using L = lat<Q>;
+    const bool hx = L::ex[i] != 0, hy = L::ey[i] != 0, hz = L::ez[i] != 0;
+    A s = (A)0;
+    if (hx) s = L::ex[i] > 0 ? ux : -ux;
+    if (hy) s = hx ? (L::ey[i] > 0 ? s + uy : s - uy) : (L::ey[i] > 0 ? uy : -uy);
+    if (hz) s = (hx || hy) ? (L::ez[i] > 0 ? s + uz : s - uz) : (L::ez[i] > 0 ? uz : -uz);
+    return s;
+}
+
+// The stored population i of node `lane` is written at byte offset lane sizeof(S) from the
+// direction's base dst + i N (below 2^32, as for the loads).
 template <int Q, typename A, typename S, bool NT = false>
-__device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, int idx,
+__device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, uint32_t lane,
                                               const float* g, A drho, A Fx, A Fy, A Fz,
                                               const Coef<A>& c)
 {
     using L = lat<Q>;
+    constexpr bool three = Q == 19;
     const A rho = c.rho_ref + drho;
     A jx = (A)0, jy = (A)0, jz = (A)0;
 #pragma unroll
@@ -90,18 +108,20 @@ __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, in
     // velocity-shift forcing: u_eq = (j + tau F) / rho
     const A ux = fmad(c.tau, Fx, jx) * inv;
     const A uy = fmad(c.tau, Fy, jy) * inv;
-    const A uz = fmad(c.tau, Fz, jz) * inv;
-    const A usq15 = (A)1.5 * (ux * ux + uy * uy + uz * uz);
+    const A uz = three ? fmad(c.tau, Fz, jz) * inv : (A)0;
+    const A usq15 = (A)1.5 * (three ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy);
+    const uint32_t boff = lane * (uint32_t)sizeof(S);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const A eu = (A)L::ex[i] * ux + (A)L::ey[i] * uy + (A)L::ez[i] * uz;
+        const A eu = e_dot<Q, A>(i, ux, uy, uz);
         const A P = fmad(eu, fmad((A)4.5, eu, (A)3), -usq15);
         const A w = weight<Q, A>(i);
         const A gi = (A)g[i];
         const A h = fmad(-w, drho, gi);
         const A d = fmad(w * rho, P, -h);
         const A gs = fmad(c.omega, d, gi);
-        put<NT, S>(dst + (int64_t)i * N + idx, store_f<S>((float)gs));
+        char* base = reinterpret_cast<char*>(dst + (int64_t)i * N);
+        put<NT, S>(reinterpret_cast<S*>(base + boff), store_f<S>((float)gs));
     }
 }
 

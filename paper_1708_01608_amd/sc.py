@@ -98,7 +98,7 @@ EXPORTS = (
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
-    "sc_hbm_probe",
+    "sc_hbm_probe", "sc_batch_tune",
 )
 
 _lib = None
@@ -152,6 +152,7 @@ def load_library(path=LIB_PATH):
         "sc_batch_destroy": (C.c_int, [P]),
         "sc_autotune": (C.c_int, [P, C.c_int32, P, C.c_int32, P]),
         "sc_hbm_probe": (C.c_int, [C.c_size_t, C.c_int32, P, P]),
+        "sc_batch_tune": (C.c_int, [P, C.c_int32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -444,6 +445,14 @@ class Batch:
                     film_node=r.film_node, film_len=r.film_len, status=r.status, lap_p=r.lap_p,
                     rho_film=r.rho_film, totals=tuple(r.totals)) for r in res]
         return out, ms.value
+
+    def tune(self, trial_steps=50):
+        """Picks the rows per thread of the box step by timing a short run of every box."""
+        rb = C.c_int32()
+        ms = (C.c_double * 3)()
+        _check(self._lib.sc_batch_tune(self._h, int(trial_steps), C.byref(rb),
+                                       C.cast(ms, C.c_void_p)))
+        return rb.value, list(ms)
 
     def density(self, k):
         nx, ny = int(self.spec.nx[k]), int(self.spec.ny[k])

@@ -92,6 +92,17 @@ def test_invalid_parameters_are_rejected_before_any_device_work(lib, field, valu
     assert lib.sc_last_error()
 
 
+def test_boxes_past_32bit_byte_offsets_are_rejected(lib):
+    # 1024 x 1024 x 1025 FP32 values need byte offsets past 2^32
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    p.lattice, p.nx, p.ny, p.nz = 19, 1024, 1024, 1025
+    h = C.c_void_p()
+    assert lib.sc_create(C.byref(p), C.byref(h)) == sc.SC_E_INVAL
+    assert b"2^32" in lib.sc_last_error()
+    assert not h.value
+
+
 def test_d3q19_needs_depth(lib):
     p = sc.Params()
     lib.sc_params_init(C.byref(p))

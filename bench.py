@@ -44,6 +44,8 @@ def parse():
                     help="oracle steps timed for cpu_baseline (0: pick ~10-30 s)")
     ap.add_argument("--variants", action="store_true",
                     help="also time FP32-compute / 16-bit storage variants (extra JSON lines)")
+    ap.add_argument("--batch-sample", type=int, default=32, metavar="N",
+                    help="batch workload: boxes also run one at a time for comparison (0: none)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also run a plain device copy of BYTES bytes (calibrates the HBM "
                          "counters of a profiler run against a kernel of known traffic)")
@@ -61,12 +63,34 @@ def bytes_per_node(q, storage):
     return 2 * q * (4 if storage == "f32" else 2)
 
 
-def step_kernel_hash():
+def kernel_hash(files=("sc_step.hip", "sc_stepcore.hpp", "sc_device.hpp")):
     h = hashlib.sha256()
-    for f in ("sc_step.hip", "sc_stepcore.hpp", "sc_device.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1708_01608_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def step_kernel_hash():
+    return kernel_hash()
+
+
+def batch_kernel_hash():
+    return kernel_hash(("sc_batch.hip", "sc_stepcore.hpp", "sc_device.hpp"))
+
+
+def batch_traffic_from_profile(compute, rows_per_thread, node_steps):
+    """HBM bytes of one whole-batch launch from the committed counter summary, if it was taken
+    on the current batch kernel source, node-slot count and workload; else None."""
+    path = os.path.join(ROOT, "profiles", f"batch_counters_{compute}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if (d.get("kernel_hash") != batch_kernel_hash() or d.get("rows_per_thread") != rows_per_thread
+            or d.get("node_steps") != node_steps):
+        return None
+    return d.get("hbm_bytes_per_launch")
 
 
 def traffic_from_profile(workload, storage, compute, tile):
@@ -135,6 +159,23 @@ def cpu_baseline(spec, sample_steps):
                        f"(FP64 collide-stream + source; test passes off), {dt:.1f} s")
 
 
+def copy_probe(nbytes):
+    """A device-to-device copy of a known size: under a counter run it calibrates the HBM
+    counters (bytes each counter reports per byte really moved)."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_probe_bytes": nbytes,
+                      "copy_GBps": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+
+
 def run_batch(args):
     """The batching pattern: every box of the batch workload in one persistent launch; one bench
     step = the whole job (every box to its merge, topological merge or max_steps)."""
@@ -164,7 +205,8 @@ def run_batch(args):
     topo = sum(1 for r in res if r["topo_step"] >= 0 and r["merge_step"] < 0)
     b.close()
     # the same kind of boxes one at a time through the single-box API (sampled)
-    sample = list(range(0, spec.n, max(1, spec.n // 32)))[:32]
+    ns = max(0, min(args.batch_sample, spec.n))
+    sample = list(range(0, spec.n, max(1, spec.n // max(ns, 1))))[:ns]
     t1 = time.perf_counter()
     ns1 = 0
     for k in sample:
@@ -175,7 +217,7 @@ def run_batch(args):
             g.step(spec.K)
         ns1 += s.N * g.t
         g.close()
-    one_by_one = ns1 / (time.perf_counter() - t1) / 1e6
+    one_by_one = ns1 / (time.perf_counter() - t1) / 1e6 if sample else None
     out = {
         "metric": "Shan-Chen MLUPS & % of HBM roofline",
         "value": round(mlups, 1),
@@ -197,13 +239,16 @@ def run_batch(args):
                    "merged_by_criterion": merged,
                    "merged_topologically_first": topo},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": batch_traffic_from_profile(compute, rows_per_thread, node_steps),
                      "kernel": "k_batch", "bytes_per_node_step": 72,
                      "kernel_ms": round(kms / args.steps, 3)},
-        "one_by_one_MLUPS": round(one_by_one, 1),
+        "one_by_one_MLUPS": round(one_by_one, 1) if one_by_one is not None else None,
         "one_by_one_sample": f"{len(sample)} boxes through sc_create/sc_step",
     }
     print(json.dumps(out), flush=True)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
 
 
 def main():
@@ -288,18 +333,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
     if args.copy_probe > 0:
-        import torch
-
-        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 5
-        print(json.dumps({"copy_probe_bytes": args.copy_probe,
-                          "copy_GBps": round(2 * args.copy_probe / dt / 1e9, 1)}), flush=True)
+        copy_probe(args.copy_probe)
     if args.variants:
         for storage, compute in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
             rv = run_gpu(spec, args, storage, compute, args.steps, args.warmup, tile)

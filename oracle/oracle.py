@@ -73,6 +73,9 @@ def _load():
     lib.orc_uniform.argtypes = [C.c_uint64, C.c_uint64]
     lib.orc_splitmix64.restype = C.c_uint64
     lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_set_barrier.restype = C.c_int
+    lib.orc_set_barrier.argtypes = [P, C.c_int, C.c_int]
+    lib.orc_owner.argtypes = [P, P]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_num_threads.argtypes = []
     _lib = lib
@@ -126,7 +129,7 @@ class OracleSim:
     """One FP64 oracle simulation (periodic box, x fastest)."""
 
     def __init__(self, q, nx, ny, nz=1, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16, amp=1e-3,
-                 seed=1, theta=0.0, K=10, film_max=8):
+                 seed=1, theta=0.0, K=10, film_max=8, barrier=False, corona=3):
         self._lib = _load()
         self.q, self.nx, self.ny, self.nz = q, nx, ny, nz
         self.d = 2 if q == 9 else 3
@@ -137,6 +140,8 @@ class OracleSim:
         if not h:
             raise ValueError("oracle rejected the parameters")
         self._h = C.c_void_p(h)
+        if barrier:
+            self.set_barrier(True, corona)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -154,6 +159,15 @@ class OracleSim:
         rc = self._lib.orc_seed_nuclei(self._h, len(r), _ptr(c), _ptr(r), _ptr(b), float(rate))
         if rc != 0:
             raise RuntimeError(f"orc_seed_nuclei returned {rc}")
+
+    def set_barrier(self, on, corona=3):
+        if self._lib.orc_set_barrier(self._h, 1 if on else 0, int(corona)) != 0:
+            raise ValueError("corona must be >= 0")
+
+    def owner(self):
+        o = np.zeros(self.N, dtype=np.int32)
+        self._lib.orc_owner(self._h, _ptr(o))
+        return o
 
     def step(self, n):
         rc = self._lib.orc_step(self._h, int(n))

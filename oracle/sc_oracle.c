@@ -134,6 +134,12 @@ struct orc_sim {
     int* merge_parent; /* criterion-merged nucleus groups (eta_m flipped to 0) */
     int* topo_parent;  /* nucleus groups that have shared a component */
 
+    /* modified Shan-Chen barrier (Sec. 3.1, Fig. 1 steps 3-6): off unless orc_set_barrier */
+    int barrier;       /* 1: bubbles interact only through the liquid until eta_m flips */
+    int corona;        /* liquid layers a bubble owns around its gas */
+    double psi_l;      /* psi(rho_l): what a bubble sees where another bubble's lattice is */
+    int32_t* owner;    /* [N] owner id of each node (0: nobody), rebuilt at every test pass */
+
     /* last test pass */
     uint32_t* labels;  /* [N] */
     int nb;
@@ -205,7 +211,13 @@ static void sc_force(const orc_sim* s, const double* psi, int64_t x, double F[3]
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < s->L.q; ++i) {
         if (s->L.e[i][0] == 0 && s->L.e[i][1] == 0 && s->L.e[i][2] == 0) continue;
-        double pn = psi[neighbour(s, x, i)];
+        int64_t y = neighbour(s, x, i);
+        double pn = psi[y];
+        /* Barrier: each bubble lives on its own lattice and meets the others only through the
+         * liquid (Sec. 3.1), so a neighbour held by a different, un-merged bubble is seen as
+         * bulk liquid. */
+        if (s->barrier && s->owner[x] != 0 && s->owner[y] != 0 && s->owner[x] != s->owner[y])
+            pn = s->psi_l;
         for (int a = 0; a < 3; ++a) acc[a] += s->L.w[i] * pn * s->L.e[i][a];
     }
     for (int a = 0; a < 3; ++a) F[a] = -s->G * psi[x] * acc[a];
@@ -241,8 +253,10 @@ orc_sim* orc_create(int q, int nx, int ny, int nz, double tau, double G, double 
     s->f = (double*)malloc(sizeof(double) * (size_t)q * (size_t)s->N);
     s->fn = (double*)malloc(sizeof(double) * (size_t)q * (size_t)s->N);
     s->labels = (uint32_t*)calloc((size_t)s->N, sizeof(uint32_t));
+    s->owner = (int32_t*)calloc((size_t)s->N, sizeof(int32_t));
+    s->psi_l = psi_of(rho_l);
     s->bub_of_label = (int*)malloc(sizeof(int) * (size_t)(s->N + 1));
-    if (!s->f || !s->fn || !s->labels || !s->bub_of_label) { orc_destroy(s); return NULL; }
+    if (!s->f || !s->fn || !s->labels || !s->owner || !s->bub_of_label) { orc_destroy(s); return NULL; }
     for (int64_t l = 0; l <= s->N; ++l) s->bub_of_label[l] = -1;
 
     /* rho(x) = rho_l + amp (2U - 1) on every node; f = f_eq(rho, 0). */
@@ -259,7 +273,7 @@ orc_sim* orc_create(int q, int nx, int ny, int nz, double tau, double G, double 
 void orc_destroy(orc_sim* s)
 {
     if (!s) return;
-    free(s->f); free(s->fn); free(s->labels); free(s->bub_of_label); free(s->bub);
+    free(s->f); free(s->fn); free(s->labels); free(s->owner); free(s->bub_of_label); free(s->bub);
     free(s->cen); free(s->rad); free(s->rem); free(s->nuc_node); free(s->comp);
     free(s->merge_parent); free(s->topo_parent); free(s->ev); free(s->tev);
     free(s);
@@ -477,6 +491,67 @@ static int cmp_u32(const void* a, const void* b)
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Owner field of the barrier.  The paper keeps each bubble on its own lattice (Fig. 1 steps   */
+/* 3-5); on one lattice this becomes an owner id per node.  A bubble owns its gas nodes and a  */
+/* corona of `corona` liquid layers, grown one lattice-neighbour layer at a time: a node that  */
+/* nobody owns takes the smallest id among its owned neighbours of the previous layer.  The id  */
+/* of a bubble is 1 + the smallest nucleus index of the criterion-merged groups (eta_m = 0) its */
+/* nuclei belong to, so merged bubbles share one lattice again.                                 */
+/* ------------------------------------------------------------------------------------------ */
+static void build_owner(orc_sim* s)
+{
+    int64_t N = s->N;
+    int* id = (int*)malloc(sizeof(int) * (size_t)(s->nb > 0 ? s->nb : 1));
+    for (int b = 0; b < s->nb; ++b) {
+        int m = -1;
+        for (int k = 0; k < s->n_nuc; ++k) {
+            if (s->comp[k] != s->bub[b].label) continue;
+            int g = uf_find(s->merge_parent, k);
+            if (m < 0 || g < m) m = g;
+        }
+        id[b] = 1 + m;
+    }
+    for (int64_t x = 0; x < N; ++x) {
+        uint32_t lab = s->labels[x];
+        int b = lab ? s->bub_of_label[lab] : -1;
+        s->owner[x] = b >= 0 ? id[b] : 0;
+    }
+    int32_t* next = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+    for (int r = 0; r < s->corona; ++r) {
+        for (int64_t x = 0; x < N; ++x) {
+            next[x] = s->owner[x];
+            if (s->owner[x] != 0) continue;
+            int32_t m = 0;
+            for (int i = 0; i < s->L.q; ++i) {
+                if (s->L.e[i][0] == 0 && s->L.e[i][1] == 0 && s->L.e[i][2] == 0) continue;
+                int32_t o = s->owner[neighbour(s, x, i)];
+                if (o != 0 && (m == 0 || o < m)) m = o;
+            }
+            next[x] = m;
+        }
+        memcpy(s->owner, next, sizeof(int32_t) * (size_t)N);
+    }
+    free(next);
+    free(id);
+}
+
+int orc_set_barrier(orc_sim* s, int on, int corona)
+{
+    if (corona < 0) return -1;
+    s->barrier = on ? 1 : 0;
+    s->corona = corona;
+    if (s->barrier) build_owner(s);
+    else memset(s->owner, 0, sizeof(int32_t) * (size_t)s->N);
+    return 0;
+}
+
+int orc_owner(const orc_sim* s, int32_t* owner)
+{
+    memcpy(owner, s->owner, sizeof(int32_t) * (size_t)s->N);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Test pass (Fig. 1 step 7 and the eta_m switch of Sec. 3.1).                                  */
 /* ------------------------------------------------------------------------------------------ */
 static int test_pass(orc_sim* s, int with_criterion)
@@ -671,6 +746,9 @@ static int test_pass(orc_sim* s, int with_criterion)
         free(fire_a);
         free(fire_b);
     }
+
+    /* the lattices of the bubbles as they stand after this pass's merges */
+    if (s->barrier) build_owner(s);
 
     free(rho);
     free(mask);

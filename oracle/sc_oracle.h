@@ -79,6 +79,15 @@ void orc_destroy(orc_sim* s);
 int orc_seed_nuclei(orc_sim* s, int n, const double* centre, const double* radius,
                     const double* budget, double rate);
 
+/* Modified Shan-Chen barrier (Sec. 3.1, Fig. 1 steps 3-6): with on != 0 every bubble owns its
+ * gas nodes and `corona` liquid layers around them, and in the force a neighbour owned by a
+ * different bubble not merged by the criterion contributes psi(rho_l) instead of its own psi.
+ * The owner field is rebuilt now and at the end of every test pass (after that pass's merges).
+ * Returns 0, or -1 if corona < 0. */
+int orc_set_barrier(orc_sim* s, int on, int corona);
+/* owner[N]: 0 = nobody, else 1 + the smallest nucleus index of the owning merged group. */
+int orc_owner(const orc_sim* s, int32_t* owner);
+
 /* Advance nsteps time steps (collide-stream, source, test pass every K steps).
  * Returns 0, or -5 once a total is not finite. */
 int orc_step(orc_sim* s, int nsteps);
@@ -87,7 +96,7 @@ int orc_step(orc_sim* s, int nsteps);
 void orc_fields(const orc_sim* s, double* rho, double* u, double* totals);
 /* p[N] = rho/3 + (G/6) psi^2 and lap[N] = 6 sum_i w_i (p(x+e_i) - p(x)); NULL skips. */
 void orc_laplacian_p(const orc_sim* s, double* p, double* lap);
-/* F[d][N], the Shan-Chen force on the current state. */
+/* F[d][N], the Shan-Chen force on the current state (with the barrier when it is on). */
 void orc_force(const orc_sim* s, double* F);
 
 /* Canonical periodic labelling of a mask: label = 1 + smallest linear index of the component,

@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
     ap.add_argument("--compute", default="auto", choices=("auto", "f32", "f64"))
     ap.add_argument("--tile", default=None, help="tx,ty,tz[,variant] of the step kernel")
+    ap.add_argument("--barrier", action="store_true",
+                    help="run the modified Shan-Chen barrier (owner field read by the step kernel)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the step-kernel autotuner before timing (default: the shape "
                          "stored by paper_1708_01608_amd.tune, else the built-in default)")
@@ -114,7 +116,8 @@ def run_gpu(spec, args, storage, compute, steps, warmup, tile=None):
     variant = 0
     if tile is not None and len(tile) == 4:
         tile, variant = tile[:3], tile[3]
-    sim = sc.Sim.from_spec(spec, storage=storage, compute=compute, tile=tile, variant=variant)
+    sim = sc.Sim.from_spec(spec, storage=storage, compute=compute, tile=tile, variant=variant,
+                           barrier=args.barrier)
     sim.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
     if tile is None and args.autotune:
         sim.autotune(trials=3)
@@ -272,11 +275,13 @@ def main():
     r = run_gpu(spec, args, args.storage, args.compute, args.steps, args.warmup, tile)
     lattice_steps = args.steps * spec.K
     mlups = spec.N * lattice_steps / r["wall"] / 1e6
-    bpn = bytes_per_node(spec.q, args.storage)
+    # the barrier adds the 2-byte owner id each node reads
+    bpn = bytes_per_node(spec.q, args.storage) + (2 if args.barrier else 0)
     bytes_per_launch = bpn * spec.N
     avg_s = r["step_ms"] / 1e3 / max(r["launches"], 1)
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = traffic_from_profile(args.workload, args.storage, r["compute"], r["tile"])
+    traffic = (None if args.barrier else
+               traffic_from_profile(args.workload, args.storage, r["compute"], r["tile"]))
     out = {
         "metric": "Shan-Chen MLUPS & % of HBM roofline",
         "value": round(mlups, 1),
@@ -303,6 +308,7 @@ def main():
             "test_every": spec.K,
             "lattice_steps_per_step": spec.K,
             "step_tile": list(r["tile"]),
+            "barrier": bool(args.barrier),
             "shape_source": ("--tile" if args.tile else "autotune" if args.autotune
                              else "tuned_shapes.json or default"),
         },
@@ -336,8 +342,10 @@ def main():
         copy_probe(args.copy_probe)
     if args.variants:
         for storage, compute in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
+            if args.barrier and storage != "f32":
+                continue  # the barrier runs on FP32 storage only
             rv = run_gpu(spec, args, storage, compute, args.steps, args.warmup, tile)
-            b = bytes_per_node(spec.q, storage) * spec.N
+            b = (bytes_per_node(spec.q, storage) + (2 if args.barrier else 0)) * spec.N
             a = b / (rv["step_ms"] / 1e3 / max(rv["launches"], 1)) / 1e9
             print(json.dumps({"variant": f"{storage} storage / {compute} compute",
                               "workload": spec.name,

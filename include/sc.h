@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 1u
+#define SC_ABI_VERSION 2u
 
 typedef enum sc_status {
     SC_OK = 0,
@@ -85,6 +85,15 @@ typedef struct sc_params {
     int32_t tile_x, tile_y, tile_z; /* step-kernel tile; 0 selects the tuned default */
     int32_t step_variant;      /* 0 default, 1 plain marching, 2 software-pipelined (D3Q19),
                                   3 plain with non-temporal population stores */
+    /* Modified Shan-Chen barrier (Sec. 3.1, Fig. 1 steps 3-6: each bubble on its own lattice,
+     * meeting the others only through the liquid until the criterion flips eta_m).  barrier = 1:
+     * every bubble owns its gas nodes and `corona` liquid layers around them (grown by lattice
+     * neighbours, ties to the smaller id); in the force a neighbour owned by a different bubble
+     * that the criterion has not merged with the node's contributes psi(rho_liquid) instead of
+     * its own psi.  Owners are rebuilt at every test pass after its merges.  FP32 storage only
+     * (SC_E_UNSUPPORTED otherwise, and with step_variant 2); at most 65534 nuclei. */
+    int32_t barrier;           /* 0 off (default), 1 on */
+    int32_t corona;            /* liquid layers a bubble owns, 0..64 (default 3) */
 } sc_params;
 
 /* One firing of the merge criterion (Sec. 3.1 eta_m: 1 -> 0; Sec. 4 film rupture). */
@@ -173,6 +182,10 @@ int sc_bubbles(struct sc_sim* sim, sc_bubble* out, int32_t cap, int32_t* n_total
 int sc_last_labels(struct sc_sim* sim, uint32_t* labels);
 /* comp[n]: label of each nucleus's node at the last pass (0: not gas); remaining[n]: budgets. */
 int sc_nuclei(struct sc_sim* sim, uint32_t* comp, double* remaining);
+/* owner[N] (host, caller-owned): the barrier's owner field as of the last test pass; 0 = no
+ * bubble, else 1 + the smallest nucleus index of the criterion-merged group that owns the node.
+ * All zero when the barrier is off.  Errors: SC_E_INVAL (NULL), SC_E_STATE, SC_E_DEVICE. */
+int sc_owner(struct sc_sim* sim, uint16_t* owner);
 int sc_time(struct sc_sim* sim, int64_t* step);
 
 /* State access for tests and checkpoints.  f is [q][N] FP64 post-streaming populations f_i(x, t)

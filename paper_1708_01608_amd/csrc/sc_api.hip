@@ -63,6 +63,11 @@ struct sc_sim {
         tmp64, mask8, nodes, list_node, list_slot, add_tab, pair_buf, res_buf, bub_tab;
     bool slots_ready = false;
 
+    // modified Shan-Chen barrier: owner id per node (uint16, fixed address for the step
+    // kernel), a second buffer for the corona layers, and the owner id of each bubble slot
+    DevBuf owner, owner2, owner_ids;
+    double psi_l = 0.0;
+
     // nuclei (Sec. 3.1) and agent budgets (Sec. 3)
     std::vector<double> cen, rad, rem;
     double rate = 0.0;
@@ -166,6 +171,28 @@ FieldArgs field_args(const sc_sim* s)
     a.Gd = s->p.G;
     a.rho_ref_d = s->rho_ref;
     a.theta = s->theta;
+    a.owner = s->p.barrier ? (const uint16_t*)s->owner.p : nullptr;
+    a.psi_ld = s->psi_l;
+    return a;
+}
+
+StepArgs step_args(const sc_sim* s)
+{
+    StepArgs a;
+    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
+    a.planes = s->shape.tile_z;
+    a.N = s->N;
+    a.tau = (float)s->p.tau;
+    a.omega = (float)(1.0 / s->p.tau);
+    a.G = (float)s->p.G;
+    a.rho_ref = (float)s->rho_ref;
+    a.taud = s->p.tau;
+    a.omegad = 1.0 / s->p.tau;
+    a.Gd = s->p.G;
+    a.rho_refd = s->rho_ref;
+    a.owner = s->p.barrier ? (const uint16_t*)s->owner.p : nullptr;
+    a.psi_l = (float)s->psi_l;
+    a.psi_ld = s->psi_l;
     return a;
 }
 
@@ -373,6 +400,43 @@ int totals_now(sc_sim* s, double out[4])
     return SC_OK;
 }
 
+// Owner field of the barrier after this pass's merges (Sec. 3.1, Fig. 1 steps 3-6): every
+// bubble's gas nodes carry 1 + the smallest nucleus index of the criterion-merged groups of its
+// nuclei, then `corona` layers grow into the liquid, a free node taking the smallest id among
+// its lattice neighbours.  The layers alternate between two buffers and the seed goes to the one
+// that makes the last layer land in s->owner, whose address the step kernel keeps.
+int build_owner(sc_sim* s, int nb)
+{
+    const FieldArgs fa = field_args(s);
+    const int r = s->p.corona;
+    uint16_t* bufs[2] = {(uint16_t*)s->owner.p, (uint16_t*)s->owner2.p};
+    int cur = r % 2;
+    const uint16_t* ids_d = nullptr;
+    if (nb > 0) {
+        std::vector<uint16_t> ids((size_t)nb);
+        for (int b = 0; b < nb; ++b) {
+            int m = -1;
+            for (int k : s->bub_nuclei[b]) {
+                const int g = uf_find(s->merge_parent, k);
+                if (m < 0 || g < m) m = g;
+            }
+            ids[b] = (uint16_t)(1 + m);
+        }
+        TRY(ensure(s, s->owner_ids, sizeof(uint16_t) * (size_t)nb));
+        HIPX(hipMemcpyAsync(s->owner_ids.p, ids.data(), sizeof(uint16_t) * nb,
+                            hipMemcpyHostToDevice, s->stream));
+        HIPX(hipStreamSynchronize(s->stream));  // ids lives on the host stack
+        ids_d = (const uint16_t*)s->owner_ids.p;
+    }
+    HIPX(launch_owner_seed((const uint32_t*)s->labels.p, nb > 0 ? (const int32_t*)s->slots.p : nullptr,
+                           ids_d, nb, bufs[cur], s->N, s->stream));
+    for (int k = 0; k < r; ++k) {
+        HIPX(launch_owner_grow(s->q, bufs[cur], bufs[cur ^ 1], fa, s->stream));
+        cur ^= 1;
+    }
+    return SC_OK;
+}
+
 int test_pass(sc_sim* s, bool with_criterion)
 {
 #pragma clang fp contract(off)
@@ -505,7 +569,6 @@ int test_pass(sc_sim* s, bool with_criterion)
             HIPX(hipStreamSynchronize(s->stream));
             s->list_count = got;
         }
-        HIPX(launch_set_slots((int32_t*)s->slots.p, (const uint32_t*)base, nb, 1, s->stream));
     }
 
     // topological merges: nuclei of one component join one group (smallest index leads)
@@ -597,6 +660,10 @@ int test_pass(sc_sim* s, bool with_criterion)
         }
     }
 
+    if (s->p.barrier) TRY(build_owner(s, nb));
+    if (nb > 0)  // slot map back to "no bubble" for the next pass
+        HIPX(launch_set_slots((int32_t*)s->slots.p, (const uint32_t*)s->bub_tab.p, nb, 1, s->stream));
+
     build_schedule(s, schedule_chunk_len(s));
     TRY(upload_schedule(s));
     TRY(prof_end(s, pe));
@@ -633,6 +700,13 @@ int validate(const sc_params* p)
     if (p->compute == SC_COMPUTE_F64 && p->storage != SC_STORE_F32)
         return fail(SC_E_UNSUPPORTED, "FP64 arithmetic is offered on FP32 storage only");
     if (!std::isfinite(p->rho_ref)) return fail(SC_E_INVAL, "rho_ref must be finite");
+    if (p->barrier != 0 && p->barrier != 1) return fail(SC_E_INVAL, "barrier must be 0 or 1");
+    if (p->barrier && (p->corona < 0 || p->corona > 64))
+        return fail(SC_E_INVAL, "corona must be in [0, 64]");
+    if (p->barrier && p->storage != SC_STORE_F32)
+        return fail(SC_E_UNSUPPORTED, "the barrier is offered on FP32 storage only");
+    if (p->barrier && p->step_variant == 2)
+        return fail(SC_E_UNSUPPORTED, "the barrier has no software-pipelined kernel");
     if (p->allocator && (!p->allocator->alloc || !p->allocator->free))
         return fail(SC_E_INVAL, "allocator needs alloc and free");
     if (p->tile_x || p->tile_y || p->tile_z || p->step_variant) {
@@ -648,7 +722,8 @@ void release(sc_sim* s)
     for (DevBuf* b : {&s->parent, &s->labels, &s->labels2, &s->slots, &s->psi, &s->rho_out,
                       &s->u_out, &s->p_out, &s->lap_out, &s->partials, &s->small, &s->tmp64,
                       &s->mask8, &s->nodes, &s->list_node, &s->list_slot, &s->add_tab,
-                      &s->pair_buf, &s->res_buf, &s->bub_tab})
+                      &s->pair_buf, &s->res_buf, &s->bub_tab, &s->owner, &s->owner2,
+                      &s->owner_ids})
         dev_free(s, b->p);
     dev_free(s, s->f[0]);
     dev_free(s, s->f[1]);
@@ -686,6 +761,8 @@ int sc_params_init(sc_params* p)
     p->film_max = 8;
     p->storage = SC_STORE_F32;
     p->rho_ref = -1.0;
+    p->barrier = 0;
+    p->corona = 3;
     return SC_OK;
 }
 
@@ -714,6 +791,9 @@ int sc_create(const sc_params* p, sc_sim** out)
         auto it = g_tuned.find(tune_key(*p, s->compute));
         if (it != g_tuned.end()) s->shape = it->second;
     }
+    // a tuned pipelined shape runs as the plain non-temporal variant under the barrier
+    if (p->barrier && s->shape.variant == 2) s->shape.variant = 3;
+    s->psi_l = 1.0 - std::exp(-p->rho_liquid);
     if (p->stream) {
         s->stream = (hipStream_t)p->stream;
     } else {
@@ -732,7 +812,17 @@ int sc_create(const sc_params* p, sc_sim** out)
         delete s;
         return fail(SC_E_NOMEM, "population buffers (" + std::to_string(2 * bytes) + " bytes)");
     }
+    if (p->barrier) {
+        const size_t ob = sizeof(uint16_t) * (size_t)s->N;
+        if (ensure(s, s->owner, ob) != SC_OK || ensure(s, s->owner2, ob) != SC_OK) {
+            release(s);
+            delete s;
+            return fail(SC_E_NOMEM, "owner field");
+        }
+    }
     hipError_t e = launch_init(s->q, p->storage, s->f[0], init_args(s, p->rho_liquid), s->stream);
+    if (e == hipSuccess && p->barrier)
+        e = launch_owner_seed(nullptr, nullptr, nullptr, 0, (uint16_t*)s->owner.p, s->N, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         std::string m = std::string("initial fill: ") + hipGetErrorString(e);
@@ -759,6 +849,7 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
     if (n < 0) return fail(SC_E_INVAL, "n must be >= 0");
     if (n > 0 && (!centre || !radius || !budget)) return fail(SC_E_INVAL, "NULL nucleus arrays");
     if (!(rate >= 0.0) || !std::isfinite(rate)) return fail(SC_E_INVAL, "rate must be finite and >= 0");
+    if (s->p.barrier && n > 65534) return fail(SC_E_INVAL, "the barrier's 16-bit owner ids allow 65534 nuclei");
     for (int k = 0; k < n; ++k) {
         for (int c = 0; c < 3; ++c)
             if (!std::isfinite(centre[3 * k + c])) return fail(SC_E_INVAL, "non-finite centre");
@@ -794,18 +885,7 @@ int sc_step(sc_sim* s, int32_t nsteps)
 {
     TRY(check_usable(s));
     if (nsteps < 0) return fail(SC_E_INVAL, "nsteps must be >= 0");
-    StepArgs a;
-    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
-    a.planes = s->shape.tile_z;
-    a.N = s->N;
-    a.tau = (float)s->p.tau;
-    a.omega = (float)(1.0 / s->p.tau);
-    a.G = (float)s->p.G;
-    a.rho_ref = (float)s->rho_ref;
-    a.taud = s->p.tau;
-    a.omegad = 1.0 / s->p.tau;
-    a.Gd = s->p.G;
-    a.rho_refd = s->rho_ref;
+    const StepArgs a = step_args(s);
     const FieldArgs fa = field_args(s);
     const int K = s->p.test_every;
     for (int it = 0; it < nsteps; ++it) {
@@ -942,6 +1022,20 @@ int sc_last_labels(sc_sim* s, uint32_t* labels)
     return SC_OK;
 }
 
+int sc_owner(sc_sim* s, uint16_t* owner)
+{
+    TRY(check_usable(s));
+    if (!owner) return fail(SC_E_INVAL, "NULL owner array");
+    if (!s->p.barrier) {
+        std::memset(owner, 0, sizeof(uint16_t) * (size_t)s->N);
+        return SC_OK;
+    }
+    HIPX(hipMemcpyAsync(owner, s->owner.p, sizeof(uint16_t) * (size_t)s->N, hipMemcpyDeviceToHost,
+                        s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
 int sc_nuclei(sc_sim* s, uint32_t* comp, double* remaining)
 {
     if (!s) return fail(SC_E_INVAL, "NULL simulation handle");
@@ -1069,12 +1163,7 @@ int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int3
 {
     TRY(check_usable(s));
     if (trials < 1 || cap < 0 || (cap > 0 && !out)) return fail(SC_E_INVAL, "bad autotune arguments");
-    StepArgs a;
-    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
-    a.N = s->N;
-    a.tau = (float)s->p.tau; a.omega = (float)(1.0 / s->p.tau);
-    a.G = (float)s->p.G; a.rho_ref = (float)s->rho_ref;
-    a.taud = s->p.tau; a.omegad = 1.0 / s->p.tau; a.Gd = s->p.G; a.rho_refd = s->rho_ref;
+    StepArgs a = step_args(s);
     const std::vector<StepShape> cand = tune_candidates(s->q);
     hipEvent_t e0, e1;
     HIPX(hipEventCreate(&e0));
@@ -1085,6 +1174,7 @@ int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int3
     int rc = SC_OK;
     for (const StepShape& sh : cand) {
         if (!step_shape_supported(s->q, sh)) continue;
+        if (s->p.barrier && sh.variant == 2) continue;  // no pipelined barrier kernel
         a.planes = sh.tile_z;
         // one untimed launch, then `trials` timed launches current -> spare buffer
         hipError_t e = launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1],

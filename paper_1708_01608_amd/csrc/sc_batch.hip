@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs b)
         float* f0 = b.pool + in.off;
         float* f1 = f0 + (int64_t)9 * N;
         uint32_t* par = b.lab + in.loff;
-        const Coef<A> c{(A)in.tau, (A)(1.0 / in.tau), (A)in.G, (A)0};
+        const Coef<A> c{(A)in.tau, (A)(1.0 / in.tau), (A)in.G, (A)0, (A)0};
         // the box's record is written by thread 0 only: keep it in LDS, not in every lane
         BatchOut& o = s_out;
         if (threadIdx.x == 0) {

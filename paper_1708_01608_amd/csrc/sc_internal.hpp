@@ -20,6 +20,11 @@ struct StepArgs {
     int64_t N;
     float tau, omega, G, rho_ref;
     double taud, omegad, Gd, rho_refd;
+    // modified Shan-Chen barrier: owner id per node (null: barrier off) and psi(rho_liquid),
+    // which a node sees where a neighbour belongs to a different, un-merged bubble
+    const uint16_t* owner;
+    float psi_l;
+    double psi_ld;
 };
 
 struct StepShape {
@@ -61,6 +66,8 @@ struct FieldArgs {
     float G;
     float rho_ref;
     double Gd, rho_ref_d, theta;
+    const uint16_t* owner;  // barrier owner field for the force in the fields (null: off)
+    double psi_ld;
 };
 hipError_t launch_psi(int q, int storage, const void* f, double* psi, const FieldArgs& a,
                       hipStream_t st);
@@ -120,6 +127,14 @@ hipError_t launch_merge(int q, int storage, const void* f, const uint32_t* label
 hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
                          const int32_t* list_slot, int64_t count, const double* add_d,
                          const FieldArgs& a, hipStream_t st);
+
+// Barrier owner field: seed = owner id of each gas node's bubble (ids_d[slot], 0 elsewhere;
+// nb == 0 writes zeros and reads neither table), then one corona layer per grow call.
+hipError_t launch_owner_seed(const uint32_t* labels, const int32_t* slot_of_root,
+                             const uint16_t* ids_d, int nb, uint16_t* owner, int64_t N,
+                             hipStream_t st);
+hipError_t launch_owner_grow(int q, const uint16_t* in, uint16_t* out, const FieldArgs& a,
+                             hipStream_t st);
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n,

@@ -43,15 +43,24 @@ __device__ __forceinline__ A sum_dev(const float* g)
 // Scalar coefficients in the arithmetic type.
 template <typename A>
 struct Coef {
-    A tau, omega, G, rho_ref;
+    A tau, omega, G, rho_ref, psi_l;
 };
 __device__ __forceinline__ Coef<float> coef_of(const StepArgs& a, float)
 {
-    return Coef<float>{a.tau, a.omega, a.G, a.rho_ref};
+    return Coef<float>{a.tau, a.omega, a.G, a.rho_ref, a.psi_l};
 }
 __device__ __forceinline__ Coef<double> coef_of(const StepArgs& a, double)
 {
-    return Coef<double>{a.taud, a.omegad, a.Gd, a.rho_refd};
+    return Coef<double>{a.taud, a.omegad, a.Gd, a.rho_refd, a.psi_ld};
+}
+
+// psi a node with owner oc sees at a neighbour with owner on: bulk liquid where the neighbour
+// belongs to a different bubble that has not merged with the node's (both ids nonzero).
+template <bool BAR, typename A>
+__device__ __forceinline__ A seen_psi(A psi_n, uint16_t oc, uint16_t on, A psi_l)
+{
+    if (BAR && oc != 0 && on != 0 && on != oc) return psi_l;
+    return psi_n;
 }
 
 // Forced BGK collision on deviations g_i = f_i - w_i rho_ref; writes f_i* - w_i rho_ref.

@@ -100,9 +100,16 @@ __global__ void k_fields(const S* f, const double* psi, float* rho_out, float* u
             j[1] += g[i] * L::ey[i];
             j[2] += g[i] * L::ez[i];
         }
+        const uint16_t oc = a.owner ? a.owner[n] : (uint16_t)0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const double pn = psi[shifted<Q>(x, y, z, i, +1, a)];
+            const int64_t m = shifted<Q>(x, y, z, i, +1, a);
+            double pn = psi[m];
+            // barrier: a neighbour of another, un-merged bubble is seen as bulk liquid
+            if (oc != 0) {
+                const uint16_t on = a.owner[m];
+                if (on != 0 && on != oc) pn = a.psi_ld;
+            }
             F[0] += L::wd[i] * pn * L::ex[i];
             F[1] += L::wd[i] * pn * L::ey[i];
             F[2] += L::wd[i] * pn * L::ez[i];
@@ -446,6 +453,46 @@ __global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_sl
     }
 }
 
+// ---- barrier owner field ---------------------------------------------------------------------
+// Seed: a gas node of a bubble (a component holding nuclei) gets that bubble's owner id.
+__global__ void k_owner_seed(const uint32_t* labels, const int32_t* slot_of_root,
+                             const uint16_t* ids, int nb, uint16_t* owner, int64_t N)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        uint16_t o = 0;
+        if (nb > 0) {
+            const uint32_t l = labels[n];
+            if (l != 0) {
+                const int32_t b = slot_of_root[l - 1];
+                if (b >= 0) o = ids[b];
+            }
+        }
+        owner[n] = o;
+    }
+}
+
+// One corona layer: a node nobody owns takes the smallest owner id among its lattice
+// neighbours (the velocity set is symmetric, so x + e_i covers the same nodes as x - e_i).
+template <int Q>
+__global__ void k_owner_grow(const uint16_t* in, uint16_t* out, FieldArgs a)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        uint16_t o = in[n];
+        if (o == 0) {
+            int x, y, z;
+            coords3(n, a.nx, a.ny, x, y, z);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const uint16_t v = in[shifted<Q>(x, y, z, i, +1, a)];
+                if (v != 0 && (o == 0 || v < o)) o = v;
+            }
+        }
+        out[n] = o;
+    }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
 {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
@@ -615,6 +662,27 @@ hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
     SC_DISPATCH(q, storage,
                 hipLaunchKernelGGL((k_source<QQ, SS>), grid_for(count), dim3(256), 0, st, (SS*)f,
                                    list_node, list_slot, count, add_d, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_owner_seed(const uint32_t* labels, const int32_t* slot_of_root,
+                             const uint16_t* ids_d, int nb, uint16_t* owner, int64_t N,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_owner_seed, grid_for(N), dim3(256), 0, st, labels, slot_of_root, ids_d,
+                       nb, owner, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_owner_grow(int q, const uint16_t* in, uint16_t* out, const FieldArgs& a,
+                             hipStream_t st)
+{
+    if (q == 9)
+        hipLaunchKernelGGL((k_owner_grow<9>), grid_for(a.N), dim3(256), 0, st, in, out, a);
+    else if (q == 19)
+        hipLaunchKernelGGL((k_owner_grow<19>), grid_for(a.N), dim3(256), 0, st, in, out, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -25,9 +25,10 @@ TOL = {
 }
 
 
-def oracle_from_spec(spec):
+def oracle_from_spec(spec, barrier=False, corona=3):
     o = OracleSim(spec.q, spec.nx, spec.ny, spec.nz, spec.tau, spec.G, spec.rho_l, spec.rho_g,
-                  spec.amp, spec.seed, spec.theta, spec.K, spec.film_max)
+                  spec.amp, spec.seed, spec.theta, spec.K, spec.film_max, barrier=barrier,
+                  corona=corona)
     o.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
     return o
 

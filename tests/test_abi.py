@@ -37,13 +37,13 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.sc_abi_version() == 1
+    assert lib.sc_abi_version() == 2
 
 
 def test_params_layout_and_defaults(lib):
     p = sc.Params()
     assert lib.sc_params_init(C.byref(p)) == sc.SC_OK
-    assert p.abi_version == 1 and p.lattice == 9 and (p.nx, p.ny, p.nz) == (128, 128, 1)
+    assert p.abi_version == 2 and p.lattice == 9 and (p.nx, p.ny, p.nz) == (128, 128, 1)
     assert p.tau == 1.0 and p.G == -5.0 and p.rho_liquid == 1.93 and p.rho_gas == 0.16
     assert p.test_every == 10 and p.film_max == 8 and p.storage == 0 and p.rho_ref == -1.0
 
@@ -90,6 +90,23 @@ def test_invalid_parameters_are_rejected_before_any_device_work(lib, field, valu
     assert lib.sc_create(C.byref(p), C.byref(h)) == sc.SC_E_INVAL
     assert not h.value
     assert lib.sc_last_error()
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("corona", -1, sc.SC_E_INVAL), ("corona", 65, sc.SC_E_INVAL), ("barrier", 2, sc.SC_E_INVAL),
+    ("storage", 1, sc.SC_E_UNSUPPORTED), ("step_variant", 2, sc.SC_E_UNSUPPORTED),
+])
+def test_barrier_parameters_are_checked(lib, field, value, code):
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    assert p.barrier == 0 and p.corona == 3
+    p.barrier = 1
+    if field == "step_variant":
+        p.lattice, p.nz, p.tile_x, p.tile_y, p.tile_z = 19, 16, 32, 8, 16
+    setattr(p, field, value)
+    h = C.c_void_p()
+    assert lib.sc_create(C.byref(p), C.byref(h)) == code
+    assert not h.value
 
 
 def test_boxes_past_32bit_byte_offsets_are_rejected(lib):

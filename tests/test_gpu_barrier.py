@@ -1,0 +1,116 @@
+"""GPU parity of the modified Shan-Chen barrier (Sec. 3.1, Fig. 1 steps 3-6) against the oracle.
+
+Owner fields are integer work and must match bit for bit; fields follow the FP32-storage /
+FP64-arithmetic bar; merge events (criterion and topological) must be the same.
+"""
+import numpy as np
+import pytest
+
+from paper_1708_01608_amd import workloads as W
+from parity import RHO_TOL, U_TOL, events_key, field_errors, gpu_from_spec, oracle_from_spec
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _spheres(gap=4, R=7.0):
+    """Two spheres of radius R on the x axis of a 44 x 24 x 24 box, `gap` liquid nodes apart."""
+    a = 10.5
+    b = a + 2 * R + gap + 1
+    return W.SimSpec(name="spheres", q=19, nx=44, ny=24, nz=24, tau=0.9, G=-5.0, rho_l=1.93,
+                     rho_g=0.16, amp=1e-3, seed=3, K=10, steps=50,
+                     centres=np.array([(a, 11.5, 11.5), (b, 11.5, 11.5)]),
+                     radii=np.array([R, R]), budgets=np.zeros(2), rate=0.0)
+
+
+def _orc_events(o):
+    from oracle.oracle import OrcEvent, OrcTopoEvent
+    ev = (OrcEvent * 64)()
+    n = o._lib.orc_events(o._h, ev, 64)
+    te = (OrcTopoEvent * 64)()
+    nt = o._lib.orc_topo_events(o._h, te, 64)
+    crit = [(e.step, e.nucleus_a, e.nucleus_b, e.label_a, e.label_b, e.film_node, e.film_len)
+            for e in ev[:n]]
+    topo = [(e.step, e.nucleus_a, e.nucleus_b) for e in te[:nt]]
+    return crit, topo
+
+
+@pytest.mark.parametrize("case", ["two_bubble", "spheres"])
+def test_barrier_owner_and_fields_match_oracle(case):
+    spec = W.two_bubble() if case == "two_bubble" else _spheres()
+    steps = 100 if case == "two_bubble" else 50
+    _announce(f"barrier {case} {steps} steps")
+    o = oracle_from_spec(spec, barrier=True)
+    g = gpu_from_spec(spec, barrier=True)
+    assert np.array_equal(g.owner().astype(np.int32), o.owner())
+    assert set(np.unique(o.owner())) == {0, 1, 2}
+    g.step(steps)
+    o.step(steps)
+    e_rho, e_u, _, _ = field_errors(g, o)
+    print(f"rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho <= RHO_TOL and e_u <= U_TOL
+    assert np.array_equal(g.owner().astype(np.int32), o.owner())
+    assert np.array_equal(g.last_labels(), o.labels())
+
+
+@pytest.mark.parametrize("gap,steps", [(4, 1000), (3, 200)])
+def test_barrier_merge_events_match_oracle(gap, steps):
+    spec = W.two_bubble(gap=gap)
+    _announce(f"barrier two_bubble gap {gap} {steps} steps")
+    o = oracle_from_spec(spec, barrier=True)
+    g = gpu_from_spec(spec, barrier=True)
+    g.step(steps)
+    o.step(steps)
+    crit, topo = _orc_events(o)
+    print("oracle", crit, topo, "\ngpu", g.merge_events(), g.topo_events())
+    assert events_key(g.merge_events()) == crit
+    assert [(e["step"], e["nucleus_a"], e["nucleus_b"]) for e in g.topo_events()] == topo
+    assert np.array_equal(g.owner().astype(np.int32), o.owner())
+    if gap == 3:  # the criterion fired at t = 10: one owner id from then on
+        assert set(np.unique(g.owner())) == {0, 1}
+
+
+@pytest.mark.parametrize("corona", [0, 1, 5])
+def test_barrier_corona_widths_match_oracle(corona):
+    spec = W.two_bubble(gap=6)
+    o = oracle_from_spec(spec, barrier=True, corona=corona)
+    g = gpu_from_spec(spec, barrier=True, corona=corona)
+    assert np.array_equal(g.owner().astype(np.int32), o.owner())
+    g.step(20)
+    o.step(20)
+    assert np.array_equal(g.owner().astype(np.int32), o.owner())
+    e_rho, e_u, _, _ = field_errors(g, o)
+    assert e_rho <= RHO_TOL and e_u <= U_TOL
+
+
+def test_barrier_invisible_while_apart_on_gpu():
+    spec = W.SimSpec(name="apart", q=9, nx=64, ny=32, nz=1, tau=0.9, G=-5.0, rho_l=1.93,
+                     rho_g=0.16, amp=1e-3, seed=1, K=10, steps=60,
+                     centres=np.array([(14.5, 15.5, 0.0), (46.5, 15.5, 0.0)]),
+                     radii=np.array([5.0, 5.0]), budgets=np.zeros(2), rate=0.0)
+    f = []
+    for bar in (False, True):
+        g = gpu_from_spec(spec, barrier=bar, tuned=False, tile=(64, 1, 4), variant=1)
+        g.step(60)
+        f.append(g.get_populations())
+        g.close()
+    assert np.array_equal(f[0], f[1])
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_barrier_tiles_and_variants_bitwise_equal(q):
+    spec = W.two_bubble(gap=3, nx=150, ny=90, radius=12.0) if q == 9 else _spheres(gap=3)
+    shapes = ([(64, 1, 3, 1), (128, 1, 8, 3), (256, 1, 64, 1)] if q == 9 else
+              [(32, 4, 5, 1), (64, 8, 16, 3), (256, 4, 64, 3), (16, 16, 7, 1)])
+    ref = None
+    for tx, ty, tz, v in shapes:
+        g = gpu_from_spec(spec, barrier=True, tile=(tx, ty, tz), variant=v)
+        g.step(30)
+        f = g.get_populations()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), (tx, ty, tz, v)
+        g.close()

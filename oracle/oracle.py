@@ -73,6 +73,10 @@ def _load():
     lib.orc_uniform.argtypes = [C.c_uint64, C.c_uint64]
     lib.orc_splitmix64.restype = C.c_uint64
     lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_set_gravity.restype = C.c_int
+    lib.orc_set_gravity.argtypes = [P, P, C.c_double]
+    lib.orc_rho0.restype = C.c_double
+    lib.orc_rho0.argtypes = [P]
     lib.orc_set_barrier.restype = C.c_int
     lib.orc_set_barrier.argtypes = [P, C.c_int, C.c_int]
     lib.orc_owner.argtypes = [P, P]
@@ -129,7 +133,8 @@ class OracleSim:
     """One FP64 oracle simulation (periodic box, x fastest)."""
 
     def __init__(self, q, nx, ny, nz=1, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16, amp=1e-3,
-                 seed=1, theta=0.0, K=10, film_max=8, barrier=False, corona=3):
+                 seed=1, theta=0.0, K=10, film_max=8, barrier=False, corona=3, gravity=None,
+                 rho0=0.0):
         self._lib = _load()
         self.q, self.nx, self.ny, self.nz = q, nx, ny, nz
         self.d = 2 if q == 9 else 3
@@ -142,6 +147,8 @@ class OracleSim:
         self._h = C.c_void_p(h)
         if barrier:
             self.set_barrier(True, corona)
+        if gravity is not None:
+            self.set_gravity(gravity, rho0)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -163,6 +170,16 @@ class OracleSim:
     def set_barrier(self, on, corona=3):
         if self._lib.orc_set_barrier(self._h, 1 if on else 0, int(corona)) != 0:
             raise ValueError("corona must be >= 0")
+
+    def set_gravity(self, g, rho0=0.0):
+        gg = np.zeros(3)
+        gg[: len(g)] = g
+        if self._lib.orc_set_gravity(self._h, _ptr(gg), float(rho0)) != 0:
+            raise ValueError("gravity and rho0 must be finite")
+
+    @property
+    def rho0(self):
+        return float(self._lib.orc_rho0(self._h))
 
     def owner(self):
         o = np.zeros(self.N, dtype=np.int32)

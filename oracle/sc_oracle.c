@@ -140,6 +140,11 @@ struct orc_sim {
     double psi_l;      /* psi(rho_l): what a bubble sees where another bubble's lattice is */
     int32_t* owner;    /* [N] owner id of each node (0: nobody), rebuilt at every test pass */
 
+    /* gravity (drainage, Sec. 3; off unless orc_set_gravity): body force (rho - rho0) g */
+    double g[3];
+    double rho0;       /* buoyancy reference density */
+    int rho0_auto;     /* rho0 = mean density, taken now and again at the seed pass */
+
     /* last test pass */
     uint32_t* labels;  /* [N] */
     int nb;
@@ -302,6 +307,25 @@ static int64_t nearest_node(const orc_sim* s, const double c[3])
 
 static int test_pass(orc_sim* s, int with_criterion);
 
+static double mean_density(const orc_sim* s)
+{
+    double M = 0.0;
+    for (int64_t x = 0; x < s->N; ++x) M += node_density(s, s->f, x);
+    return M / (double)s->N;
+}
+
+int orc_set_gravity(orc_sim* s, const double* g, double rho0)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(g[a])) return -1;
+        s->g[a] = (a < s->L.d) ? g[a] : 0.0;
+    }
+    if (!isfinite(rho0)) return -1;
+    s->rho0_auto = rho0 <= 0.0;
+    s->rho0 = s->rho0_auto ? mean_density(s) : rho0;
+    return 0;
+}
+
 int orc_seed_nuclei(orc_sim* s, int n, const double* centre, const double* radius,
                     const double* budget, double rate)
 {
@@ -348,6 +372,8 @@ int orc_seed_nuclei(orc_sim* s, int n, const double* centre, const double* radiu
             for (int i = 0; i < q; ++i) s->f[(int64_t)i * N + x] = feq_one(&s->L, i, rho, zero);
         }
     }
+    /* the buoyancy reference follows the seeded box when it is the mean density */
+    if (s->rho0_auto) s->rho0 = mean_density(s);
     /* The pass run by seeding labels the painted bubbles but does not evaluate the criterion:
      * a painted step profile has no film yet, and p(rho_g) ~ p(rho_l) there. */
     return test_pass(s, 0);
@@ -371,6 +397,8 @@ static void collide_stream(orc_sim* s)
         double j[3], F[3], u[3], ueq[3];
         node_momentum(s, s->f, x, j);
         sc_force(s, psi, x, F);
+        /* gravity: buoyancy body force relative to rho0 */
+        for (int a = 0; a < 3; ++a) F[a] += (rho - s->rho0) * s->g[a];
         /* Original Shan-Chen forcing: the equilibrium velocity is shifted by tau F / rho. */
         for (int a = 0; a < 3; ++a) {
             u[a] = j[a] / rho;
@@ -789,7 +817,8 @@ void orc_fields(const orc_sim* s, double* rho, double* u, double* totals)
                 double j[3], F[3];
                 node_momentum(s, s->f, x, j);
                 sc_force(s, psi, x, F);
-                /* reported velocity: (j + F/2) / rho */
+                for (int a = 0; a < 3; ++a) F[a] += (r - s->rho0) * s->g[a];
+                /* reported velocity: (j + F/2) / rho, F with the body force */
                 for (int a = 0; a < d; ++a) u[(int64_t)a * N + x] = (j[a] + 0.5 * F[a]) / r;
             }
         }
@@ -871,6 +900,7 @@ void orc_set_equilibrium(orc_sim* s, const double* rho, const double* u)
 }
 
 int64_t orc_time(const orc_sim* s) { return s->t; }
+double orc_rho0(const orc_sim* s) { return s->rho0; }
 int64_t orc_num_nodes(const orc_sim* s) { return s->N; }
 
 int orc_labels(const orc_sim* s, uint32_t* labels)

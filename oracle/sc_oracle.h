@@ -88,6 +88,14 @@ int orc_set_barrier(orc_sim* s, int on, int corona);
 /* owner[N]: 0 = nobody, else 1 + the smallest nucleus index of the owning merged group. */
 int orc_owner(const orc_sim* s, int32_t* owner);
 
+/* Gravity (drainage; the paper's runs leave it out): a body force (rho - rho0) g is added to the
+ * Shan-Chen force of every node, in the collision and in the reported velocity.  g is [3] (z
+ * ignored in 2D).  rho0 <= 0 selects the mean density of the box, taken now and again when
+ * nuclei are seeded, which makes the net body force zero.  Returns 0, or -1 if not finite. */
+int orc_set_gravity(orc_sim* s, const double* g, double rho0);
+/* The buoyancy reference density in use. */
+double orc_rho0(const orc_sim* s);
+
 /* Advance nsteps time steps (collide-stream, source, test pass every K steps).
  * Returns 0, or -5 once a total is not finite. */
 int orc_step(orc_sim* s, int nsteps);

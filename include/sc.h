@@ -94,6 +94,13 @@ typedef struct sc_params {
      * (SC_E_UNSUPPORTED otherwise, and with step_variant 2); at most 65534 nuclei. */
     int32_t barrier;           /* 0 off (default), 1 on */
     int32_t corona;            /* liquid layers a bubble owns, 0..64 (default 3) */
+    /* Gravity for drainage studies (the paper's runs leave it out): a body force
+     * (rho - rho0) g is added to the Shan-Chen force of every node, in the step and in the
+     * reported velocity.  rho0 = rho_buoyancy if > 0, else the mean density of the box, taken at
+     * sc_create and again at sc_seed_nuclei (no net force on the periodic box).  FP32 storage
+     * only (SC_E_UNSUPPORTED otherwise, and with step_variant 2); gravity[2] is ignored in 2D. */
+    double gravity[3];         /* g in lattice units; all zero (default) = off */
+    double rho_buoyancy;       /* rho0; <= 0 selects the mean density */
 } sc_params;
 
 /* One firing of the merge criterion (Sec. 3.1 eta_m: 1 -> 0; Sec. 4 film rupture). */
@@ -186,6 +193,8 @@ int sc_nuclei(struct sc_sim* sim, uint32_t* comp, double* remaining);
  * bubble, else 1 + the smallest nucleus index of the criterion-merged group that owns the node.
  * All zero when the barrier is off.  Errors: SC_E_INVAL (NULL), SC_E_STATE, SC_E_DEVICE. */
 int sc_owner(struct sc_sim* sim, uint16_t* owner);
+/* *rho0: the buoyancy reference density in use (0 when gravity is off).  Errors: SC_E_INVAL. */
+int sc_buoyancy_density(struct sc_sim* sim, double* rho0);
 int sc_time(struct sc_sim* sim, int64_t* step);
 
 /* State access for tests and checkpoints.  f is [q][N] FP64 post-streaming populations f_i(x, t)

@@ -68,6 +68,10 @@ struct sc_sim {
     DevBuf owner, owner2, owner_ids;
     double psi_l = 0.0;
 
+    // gravity: buoyancy reference density (the mean density when rho_buoyancy <= 0)
+    bool grav = false;
+    double rho0 = 0.0;
+
     // nuclei (Sec. 3.1) and agent budgets (Sec. 3)
     std::vector<double> cen, rad, rem;
     double rate = 0.0;
@@ -173,6 +177,9 @@ FieldArgs field_args(const sc_sim* s)
     a.theta = s->theta;
     a.owner = s->p.barrier ? (const uint16_t*)s->owner.p : nullptr;
     a.psi_ld = s->psi_l;
+    a.grav = s->grav ? 1 : 0;
+    for (int c = 0; c < 3; ++c) a.gd[c] = s->p.gravity[c];
+    a.rho0d = s->rho0;
     return a;
 }
 
@@ -193,6 +200,13 @@ StepArgs step_args(const sc_sim* s)
     a.owner = s->p.barrier ? (const uint16_t*)s->owner.p : nullptr;
     a.psi_l = (float)s->psi_l;
     a.psi_ld = s->psi_l;
+    a.grav = s->grav ? 1 : 0;
+    for (int c = 0; c < 3; ++c) {
+        a.gd[c] = s->p.gravity[c];
+        a.g[c] = (float)s->p.gravity[c];
+    }
+    a.rho0d = s->rho0;
+    a.rho0 = (float)s->rho0;
     return a;
 }
 
@@ -434,6 +448,20 @@ int build_owner(sc_sim* s, int nb)
         HIPX(launch_owner_grow(s->q, bufs[cur], bufs[cur ^ 1], fa, s->stream));
         cur ^= 1;
     }
+    return SC_OK;
+}
+
+// Buoyancy reference: the given density, or the mean density M/N of the box as it stands (at
+// creation and again when nuclei are seeded).
+int set_rho0(sc_sim* s)
+{
+    if (s->p.rho_buoyancy > 0.0) {
+        s->rho0 = s->p.rho_buoyancy;
+        return SC_OK;
+    }
+    double tot[4];
+    TRY(totals_now(s, tot));
+    s->rho0 = tot[0] / (double)s->N;
     return SC_OK;
 }
 
@@ -707,6 +735,17 @@ int validate(const sc_params* p)
         return fail(SC_E_UNSUPPORTED, "the barrier is offered on FP32 storage only");
     if (p->barrier && p->step_variant == 2)
         return fail(SC_E_UNSUPPORTED, "the barrier has no software-pipelined kernel");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(p->gravity[c])) return fail(SC_E_INVAL, "gravity must be finite");
+    if (!std::isfinite(p->rho_buoyancy)) return fail(SC_E_INVAL, "rho_buoyancy must be finite");
+    {
+        const bool g_on = p->gravity[0] != 0.0 || p->gravity[1] != 0.0 ||
+                          (p->lattice == SC_D3Q19 && p->gravity[2] != 0.0);
+        if (g_on && p->storage != SC_STORE_F32)
+            return fail(SC_E_UNSUPPORTED, "gravity is offered on FP32 storage only");
+        if (g_on && p->step_variant == 2)
+            return fail(SC_E_UNSUPPORTED, "gravity has no software-pipelined kernel");
+    }
     if (p->allocator && (!p->allocator->alloc || !p->allocator->free))
         return fail(SC_E_INVAL, "allocator needs alloc and free");
     if (p->tile_x || p->tile_y || p->tile_z || p->step_variant) {
@@ -791,8 +830,11 @@ int sc_create(const sc_params* p, sc_sim** out)
         auto it = g_tuned.find(tune_key(*p, s->compute));
         if (it != g_tuned.end()) s->shape = it->second;
     }
-    // a tuned pipelined shape runs as the plain non-temporal variant under the barrier
-    if (p->barrier && s->shape.variant == 2) s->shape.variant = 3;
+    s->grav = p->gravity[0] != 0.0 || p->gravity[1] != 0.0 ||
+              (p->lattice == SC_D3Q19 && p->gravity[2] != 0.0);
+    if (p->lattice == SC_D2Q9) s->p.gravity[2] = 0.0;
+    // a tuned pipelined shape runs as the plain non-temporal variant of the extended kernels
+    if ((p->barrier || s->grav) && s->shape.variant == 2) s->shape.variant = 3;
     s->psi_l = 1.0 - std::exp(-p->rho_liquid);
     if (p->stream) {
         s->stream = (hipStream_t)p->stream;
@@ -829,6 +871,14 @@ int sc_create(const sc_params* p, sc_sim** out)
         release(s);
         delete s;
         return fail(SC_E_DEVICE, m);
+    }
+    if (s->grav) {
+        const int rc = set_rho0(s);
+        if (rc != SC_OK) {
+            release(s);
+            delete s;
+            return rc;
+        }
     }
     *out = s;
     return SC_OK;
@@ -878,6 +928,7 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
         HIPX(launch_paint(s->q, s->p.storage, s->f[s->cur], ia, &s->cen[3 * k], s->rad[k],
                           s->stream));
     }
+    if (s->grav) TRY(set_rho0(s));
     return test_pass(s, false);
 }
 
@@ -1019,6 +1070,14 @@ int sc_last_labels(sc_sim* s, uint32_t* labels)
     HIPX(hipMemcpyAsync(labels, s->labels.p, sizeof(uint32_t) * (size_t)s->N,
                         hipMemcpyDeviceToHost, s->stream));
     HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_buoyancy_density(sc_sim* s, double* rho0)
+{
+    TRY(check_usable(s));
+    if (!rho0) return fail(SC_E_INVAL, "NULL output");
+    *rho0 = s->rho0;
     return SC_OK;
 }
 

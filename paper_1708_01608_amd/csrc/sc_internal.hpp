@@ -25,6 +25,10 @@ struct StepArgs {
     const uint16_t* owner;
     float psi_l;
     double psi_ld;
+    // gravity: body force (rho - rho0) g added to the Shan-Chen force (grav = 0: off)
+    int grav;
+    float g[3], rho0;
+    double gd[3], rho0d;
 };
 
 struct StepShape {
@@ -68,6 +72,8 @@ struct FieldArgs {
     double Gd, rho_ref_d, theta;
     const uint16_t* owner;  // barrier owner field for the force in the fields (null: off)
     double psi_ld;
+    int grav;               // gravity body force (rho - rho0) g in the reported velocity
+    double gd[3], rho0d;
 };
 hipError_t launch_psi(int q, int storage, const void* f, double* psi, const FieldArgs& a,
                       hipStream_t st);

@@ -45,14 +45,16 @@ __device__ __forceinline__ int logical_block(const StepGrid& g)
 // ------------------------------------------------------------------------------------------
 // D2Q9: a block owns TX nodes of a row and marches `planes` rows in y.
 // ------------------------------------------------------------------------------------------
-template <typename S, typename A, int TX, bool NT = false, bool BAR = false>
+template <typename S, typename A, int TX, bool NT = false, bool EXT = false>
 __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __restrict__ dst,
                                                StepArgs a, StepGrid grid)
 {
     using L = lat<9>;
     __shared__ A ps[4][TX + 2];
-    __shared__ uint16_t po[BAR ? 4 : 1][BAR ? TX + 2 : 1];  // owners beside psi (barrier)
+    __shared__ uint16_t po[EXT ? 4 : 1][EXT ? TX + 2 : 1];  // owners beside psi (barrier)
+    // extended kernels: barrier when an owner field is given, gravity when c.grav
     const uint16_t* __restrict__ ownr = a.owner;
+    const bool bar = EXT && ownr != nullptr;
     const Coef<A> c = coef_of(a, A());
     const int nx = a.nx, ny = a.ny;
     const int64_t N = a.N;
@@ -83,13 +85,13 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
             float g[9];
             pull_node<9>(src, N, nx, ny, x, xm, xp, y, ym, yp, 0, 0, 0, g);
             ps[0][tx + 1] = psi_f(c.rho_ref + sum_dev<9, A>(g));
-            if constexpr (BAR) po[0][tx + 1] = ownr[x + (int64_t)nx * y];
+            if constexpr (EXT) if (bar) po[0][tx + 1] = ownr[x + (int64_t)nx * y];
         }
         if (ring) {
             float h[9];
             pull_node<9>(src, N, nx, ny, hx, hxm, hxp, y, ym, yp, 0, 0, 0, h);
             ps[0][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
-            if constexpr (BAR) po[0][hl] = ownr[hx + (int64_t)nx * y];
+            if constexpr (EXT) if (bar) po[0][hl] = ownr[hx + (int64_t)nx * y];
         }
     }
     {
@@ -99,13 +101,13 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
             pull_node<9>(src, N, nx, ny, x, xm, xp, y, ym, yp, 0, 0, 0, cur);
             dcur = sum_dev<9, A>(cur);
             ps[1][tx + 1] = psi_f(c.rho_ref + dcur);
-            if constexpr (BAR) po[1][tx + 1] = ownr[x + (int64_t)nx * y];
+            if constexpr (EXT) if (bar) po[1][tx + 1] = ownr[x + (int64_t)nx * y];
         }
         if (ring) {
             float h[9];
             pull_node<9>(src, N, nx, ny, hx, hxm, hxp, y, ym, yp, 0, 0, 0, h);
             ps[1][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
-            if constexpr (BAR) po[1][hl] = ownr[hx + (int64_t)nx * y];
+            if constexpr (EXT) if (bar) po[1][hl] = ownr[hx + (int64_t)nx * y];
         }
     }
 
@@ -119,32 +121,33 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
                 pull_node<9>(src, N, nx, ny, x, xm, xp, yn, ym, yp, 0, 0, 0, nxt);
                 dnxt = sum_dev<9, A>(nxt);
                 ps[sn][tx + 1] = psi_f(c.rho_ref + dnxt);
-                if constexpr (BAR) po[sn][tx + 1] = ownr[x + (int64_t)nx * yn];
+                if constexpr (EXT) if (bar) po[sn][tx + 1] = ownr[x + (int64_t)nx * yn];
             }
             if (ring) {
                 float h[9];
                 pull_node<9>(src, N, nx, ny, hx, hxm, hxp, yn, ym, yp, 0, 0, 0, h);
                 ps[sn][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
-                if constexpr (BAR) po[sn][hl] = ownr[hx + (int64_t)nx * yn];
+                if constexpr (EXT) if (bar) po[sn][hl] = ownr[hx + (int64_t)nx * yn];
             }
         }
         __syncthreads();
         if (own) {
             const A pc = ps[s][tx + 1];
             uint16_t oc = 0;
-            if constexpr (BAR) oc = po[s][tx + 1];
+            if constexpr (EXT) if (bar) oc = po[s][tx + 1];
             A fx = (A)0, fy = (A)0;
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 const int slot = L::ey[i] > 0 ? sn : (L::ey[i] < 0 ? sp : s);
                 A psn = ps[slot][tx + 1 + L::ex[i]];
-                if constexpr (BAR) psn = seen_psi<BAR>(psn, oc, po[slot][tx + 1 + L::ex[i]], c.psi_l);
+                if constexpr (EXT)
+                    if (bar) psn = seen_psi<true>(psn, oc, po[slot][tx + 1 + L::ex[i]], c.psi_l);
                 const A pn = weight<9, A>(i) * psn;
                 if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
                 if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
             }
             const A gp = -c.G * pc;
-            collide_store<9, A, S, NT>(dst, N, (uint32_t)(x + nx * y), cur, dcur, gp * fx,
+            collide_store<9, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * y), cur, dcur, gp * fx,
                                        gp * fy, (A)0, c);
         }
 #pragma unroll
@@ -156,14 +159,16 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
 // ------------------------------------------------------------------------------------------
 // D3Q19: a block owns a TX x TY tile of an x-y plane and marches `planes` planes in z.
 // ------------------------------------------------------------------------------------------
-template <typename S, typename A, int TX, int TY, bool NT = false, bool BAR = false>
+template <typename S, typename A, int TX, int TY, bool NT = false, bool EXT = false>
 __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S* __restrict__ dst,
                                                    StepArgs a, StepGrid grid)
 {
     using L = lat<19>;
     __shared__ A ps[4][TY + 2][TX + 2];
-    __shared__ uint16_t po[BAR ? 4 : 1][BAR ? TY + 2 : 1][BAR ? TX + 2 : 1];  // owners (barrier)
+    __shared__ uint16_t po[EXT ? 4 : 1][EXT ? TY + 2 : 1][EXT ? TX + 2 : 1];  // owners (barrier)
+    // extended kernels: barrier when an owner field is given, gravity when c.grav
     const uint16_t* __restrict__ ownr = a.owner;
+    const bool bar = EXT && ownr != nullptr;
     const Coef<A> c = coef_of(a, A());
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t N = a.N;
@@ -209,13 +214,15 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
             float g[19];
             pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z, zm, zp, g);
             ps[0][ty + 1][tx + 1] = psi_f(c.rho_ref + sum_dev<19, A>(g));
-            if constexpr (BAR) po[0][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * z)];
+            if constexpr (EXT)
+                if (bar) po[0][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * z)];
         }
         if (ring) {
             float h[19];
             pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z, zm, zp, h);
             ps[0][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
-            if constexpr (BAR) po[0][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * z)];
+            if constexpr (EXT)
+                if (bar) po[0][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * z)];
         }
     }
     {
@@ -225,13 +232,15 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
             pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z, zm, zp, cur);
             dcur = sum_dev<19, A>(cur);
             ps[1][ty + 1][tx + 1] = psi_f(c.rho_ref + dcur);
-            if constexpr (BAR) po[1][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * z)];
+            if constexpr (EXT)
+                if (bar) po[1][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * z)];
         }
         if (ring) {
             float h[19];
             pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z, zm, zp, h);
             ps[1][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
-            if constexpr (BAR) po[1][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * z)];
+            if constexpr (EXT)
+                if (bar) po[1][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * z)];
         }
     }
 
@@ -245,37 +254,40 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
                 pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, zn, zm, zp, nxt);
                 dnxt = sum_dev<19, A>(nxt);
                 ps[sn][ty + 1][tx + 1] = psi_f(c.rho_ref + dnxt);
-                if constexpr (BAR)
-                    po[sn][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * zn)];
+                if constexpr (EXT)
+                    if (bar)
+                        po[sn][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * zn)];
             }
             if (ring) {
                 float h[19];
                 pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, zn, zm, zp, h);
                 ps[sn][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
-                if constexpr (BAR)
-                    po[sn][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * zn)];
+                if constexpr (EXT)
+                    if (bar)
+                        po[sn][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * zn)];
             }
         }
         __syncthreads();
         if (own) {
             const A pc = ps[s][ty + 1][tx + 1];
             uint16_t oc = 0;
-            if constexpr (BAR) oc = po[s][ty + 1][tx + 1];
+            if constexpr (EXT) if (bar) oc = po[s][ty + 1][tx + 1];
             A fx = (A)0, fy = (A)0, fz = (A)0;
 #pragma unroll
             for (int i = 1; i < 19; ++i) {
                 const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
                 A psn = ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
-                if constexpr (BAR)
-                    psn = seen_psi<BAR>(psn, oc, po[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]],
-                                        c.psi_l);
+                if constexpr (EXT)
+                    if (bar)
+                        psn = seen_psi<true>(
+                            psn, oc, po[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]], c.psi_l);
                 const A pn = weight<19, A>(i) * psn;
                 if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
                 if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
                 if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
             }
             const A gp = -c.G * pc;
-            collide_store<19, A, S, NT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
+            collide_store<19, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
                                         gp * fx, gp * fy, gp * fz, c);
         }
 #pragma unroll
@@ -445,14 +457,15 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
     const int nb = g.gx * g.gy * g.gz;
     g.remap = (nb % 8 == 0) ? 1 : 0;
     dim3 grid(nb);
-    // the barrier variants exist for FP32 storage (either arithmetic), marching kernels only
+    // the extended kernels (barrier and/or gravity) exist for FP32 storage (either arithmetic),
+    // marching variants only
     constexpr bool kBarOK = std::is_same<S, float>::value;
-    const bool bar = a.owner != nullptr;
-    if (bar && (!kBarOK || s.variant == 2)) return hipErrorInvalidValue;
+    const bool ext = a.owner != nullptr || a.grav != 0;
+    if (ext && (!kBarOK || s.variant == 2)) return hipErrorInvalidValue;
 #define SC_L2(TX)                                                                                \
     if (s.tile_x == TX) {                                                                        \
         if constexpr (kBarOK) {                                                                  \
-            if (bar) {                                                                           \
+            if (ext) {                                                                           \
                 if (s.variant == 3)                                                              \
                     hipLaunchKernelGGL((k_step2d<S, A, TX, true, true>), grid, dim3(TX), 0, st,  \
                                        src, dst, a, g);                                          \
@@ -472,7 +485,7 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
 #define SC_L3(TX, TY)                                                                            \
     if (s.tile_x == TX && s.tile_y == TY) {                                                      \
         if constexpr (kBarOK) {                                                                  \
-            if (bar) {                                                                           \
+            if (ext) {                                                                           \
                 if (s.variant == 3)                                                              \
                     hipLaunchKernelGGL((k_step3d<S, A, TX, TY, true, true>), grid,               \
                                        dim3(TX * TY), 0, st, src, dst, a, g);                    \

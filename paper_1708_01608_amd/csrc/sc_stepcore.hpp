@@ -44,14 +44,18 @@ __device__ __forceinline__ A sum_dev(const float* g)
 template <typename A>
 struct Coef {
     A tau, omega, G, rho_ref, psi_l;
+    A gx, gy, gz, rho0;  // gravity (used by the extended kernels when grav != 0)
+    int grav;
 };
 __device__ __forceinline__ Coef<float> coef_of(const StepArgs& a, float)
 {
-    return Coef<float>{a.tau, a.omega, a.G, a.rho_ref, a.psi_l};
+    return Coef<float>{a.tau, a.omega, a.G, a.rho_ref, a.psi_l,
+                       a.g[0], a.g[1], a.g[2], a.rho0, a.grav};
 }
 __device__ __forceinline__ Coef<double> coef_of(const StepArgs& a, double)
 {
-    return Coef<double>{a.taud, a.omegad, a.Gd, a.rho_refd, a.psi_ld};
+    return Coef<double>{a.taud, a.omegad, a.Gd, a.rho_refd, a.psi_ld,
+                        a.gd[0], a.gd[1], a.gd[2], a.rho0d, a.grav};
 }
 
 // psi a node with owner oc sees at a neighbour with owner on: bulk liquid where the neighbour
@@ -98,7 +102,7 @@ __device__ __forceinline__ A e_dot(int i, A ux, A uy, A uz)
 
 // The stored population i of node `lane` is written at byte offset lane sizeof(S) from the
 // direction's base dst + i N (below 2^32, as for the loads).
-template <int Q, typename A, typename S, bool NT = false>
+template <int Q, typename A, typename S, bool NT = false, bool EXT = false>
 __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, uint32_t lane,
                                               const float* g, A drho, A Fx, A Fy, A Fz,
                                               const Coef<A>& c)
@@ -106,6 +110,14 @@ __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, ui
     using L = lat<Q>;
     constexpr bool three = Q == 19;
     const A rho = c.rho_ref + drho;
+    if constexpr (EXT) {
+        if (c.grav) {  // gravity: buoyancy body force relative to rho0
+            const A dr = (c.rho_ref - c.rho0) + drho;
+            Fx = fmad(dr, c.gx, Fx);
+            Fy = fmad(dr, c.gy, Fy);
+            if (three) Fz = fmad(dr, c.gz, Fz);
+        }
+    }
     A jx = (A)0, jy = (A)0, jz = (A)0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {

@@ -116,7 +116,8 @@ __global__ void k_fields(const S* f, const double* psi, float* rho_out, float* u
         }
         const double pc = psi[n];
         for (int c = 0; c < L::d; ++c) {
-            const double Fc = -a.Gd * pc * F[c];
+            double Fc = -a.Gd * pc * F[c];
+            if (a.grav) Fc += (rho - a.rho0d) * a.gd[c];  // gravity body force
             u_out[(int64_t)c * a.N + n] = (float)((j[c] + 0.5 * Fc) / rho);
         }
     }

@@ -45,6 +45,7 @@ class Params(C.Structure):
         ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
         ("step_variant", C.c_int32),
         ("barrier", C.c_int32), ("corona", C.c_int32),
+        ("gravity", C.c_double * 3), ("rho_buoyancy", C.c_double),
     ]
 
 
@@ -95,7 +96,7 @@ class BatchResult(C.Structure):
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
     "sc_seed_nuclei", "sc_step", "sc_fields", "sc_laplacian_p", "sc_label_bubbles",
-    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_owner", "sc_time",
+    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_owner", "sc_buoyancy_density", "sc_time",
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
@@ -137,6 +138,7 @@ def load_library(path=LIB_PATH):
         "sc_last_labels": (C.c_int, [P, P]),
         "sc_nuclei": (C.c_int, [P, P, P]),
         "sc_owner": (C.c_int, [P, P]),
+        "sc_buoyancy_density": (C.c_int, [P, P]),
         "sc_time": (C.c_int, [P, P]),
         "sc_lattice": (C.c_int, [C.c_int32, P, P]),
         "sc_get_populations": (C.c_int, [P, P]),
@@ -235,7 +237,7 @@ class Sim:
     def __init__(self, q=9, nx=128, ny=128, nz=1, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16,
                  amp=1e-3, seed=1, theta=0.0, K=10, film_max=8, storage="f32", compute="auto",
                  rho_ref=-1.0, tile=None, variant=0, memory="torch", tuned=True, barrier=False,
-                 corona=3):
+                 corona=3, gravity=None, rho0=0.0):
         self._lib = load_library()
         self._h = None
         p = Params()
@@ -250,12 +252,16 @@ class Sim:
         comp_name = compute if isinstance(compute, str) else {0: "auto", 1: "f32", 2: "f64"}[compute]
         if tile is None and tuned:
             tile, variant = _tuned_shape(q, nx, ny, nz, storage, comp_name, variant)
-            if barrier and variant == 2:  # no pipelined barrier kernel: same tile, plain variant
-                variant = 3
+            if (barrier or gravity is not None) and variant == 2:
+                variant = 3  # no pipelined extended kernel: same tile, plain variant
         if tile is not None:
             p.tile_x, p.tile_y, p.tile_z = tile
         p.step_variant = int(variant)
         p.barrier, p.corona = (1 if barrier else 0), int(corona)
+        if gravity is not None:
+            for c, v in enumerate(gravity):
+                p.gravity[c] = float(v)
+        p.rho_buoyancy = float(rho0)
         self.mem = None
         if memory == "torch":
             self.mem = TorchMemory()
@@ -330,6 +336,13 @@ class Sim:
         nc = C.c_int64()
         _check(self._lib.sc_label_bubbles(self._h, _ptr(m), _ptr(lab), C.byref(nc)))
         return lab, nc.value
+
+    @property
+    def rho0(self):
+        """Buoyancy reference density of the gravity body force (0 when gravity is off)."""
+        v = C.c_double()
+        _check(self._lib.sc_buoyancy_density(self._h, C.byref(v)))
+        return v.value
 
     def owner(self):
         """Owner field of the barrier (uint16, 0 = no bubble) as of the last test pass."""

@@ -109,6 +109,21 @@ def test_barrier_parameters_are_checked(lib, field, value, code):
     assert not h.value
 
 
+@pytest.mark.parametrize("g,storage,variant,code", [
+    ((float("nan"), 0.0, 0.0), 0, 0, sc.SC_E_INVAL), ((0.0, 1e-5, 0.0), 2, 0, sc.SC_E_UNSUPPORTED),
+])
+def test_gravity_parameters_are_checked(lib, g, storage, variant, code):
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    assert list(p.gravity) == [0.0, 0.0, 0.0] and p.rho_buoyancy == 0.0
+    for c in range(3):
+        p.gravity[c] = g[c]
+    p.storage, p.step_variant = storage, variant
+    h = C.c_void_p()
+    assert lib.sc_create(C.byref(p), C.byref(h)) == code
+    assert not h.value
+
+
 def test_boxes_past_32bit_byte_offsets_are_rejected(lib):
     # 1024 x 1024 x 1025 FP32 values need byte offsets past 2^32
     p = sc.Params()

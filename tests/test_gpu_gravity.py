@@ -1,0 +1,81 @@
+"""GPU parity of the gravity body force (rho - rho0) g against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import OracleSim
+from paper_1708_01608_amd import sc
+from paper_1708_01608_amd import workloads as W
+from parity import RHO_TOL, U_TOL, field_errors, gpu_from_spec
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _pair(spec, g, barrier=False, **kw):
+    # gravity is set before seeding on both sides, so both take rho0 = mean of the seeded box
+    o = OracleSim(spec.q, spec.nx, spec.ny, spec.nz, spec.tau, spec.G, spec.rho_l, spec.rho_g,
+                  spec.amp, spec.seed, spec.theta, spec.K, spec.film_max, barrier=barrier,
+                  gravity=g)
+    o.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
+    return o, gpu_from_spec(spec, gravity=g, barrier=barrier, **kw)
+
+
+@pytest.mark.parametrize("case", ["two_bubble", "spheres_barrier"])
+def test_gravity_fields_match_oracle(case):
+    if case == "two_bubble":
+        spec, g, barrier, steps = W.two_bubble(), (0.0, -2e-5), False, 100
+    else:
+        spec = W.SimSpec(name="spheres", q=19, nx=44, ny=24, nz=24, tau=0.9, G=-5.0, rho_l=1.93,
+                         rho_g=0.16, amp=1e-3, seed=3, K=10, steps=50,
+                         centres=np.array([(10.5, 11.5, 11.5), (32.5, 11.5, 11.5)]),
+                         radii=np.array([7.0, 7.0]), budgets=np.zeros(2), rate=0.0)
+        g, barrier, steps = (1e-5, 0.0, -3e-5), True, 50
+    _announce(f"gravity {case} {steps} steps")
+    o, gpu = _pair(spec, g, barrier)
+    assert abs(gpu.rho0 - o.rho0) <= 1e-7 * o.rho0
+    gpu.step(steps)
+    o.step(steps)
+    e_rho, e_u, _, _ = field_errors(gpu, o)
+    print(f"rho {e_rho:.3e} u {e_u:.3e} rho0 gpu {gpu.rho0:.12f} oracle {o.rho0:.12f}")
+    assert e_rho <= RHO_TOL and e_u <= U_TOL
+    assert np.array_equal(gpu.last_labels(), o.labels())
+
+
+@pytest.mark.parametrize("q,shape", [(9, (16, 12, 1)), (19, (8, 6, 5))])
+def test_gravity_momentum_closed_form_on_gpu(q, shape):
+    # G = 0, uniform rho = 1.3, rho0 = 1.0: J(t) = t N 0.3 g.  The populations are stored in
+    # FP32 and every node of a uniform box rounds alike, so the per-step increment must stand
+    # well above one ulp of the populations (~3e-8): g ~ 1e-3 gives 3e-4 per node and step.
+    nx, ny, nz = shape
+    g = (1e-3, -5e-4, 1.5e-3)[: 2 if q == 9 else 3]
+    s = sc.Sim(q=q, nx=nx, ny=ny, nz=nz, tau=0.8, G=0.0, rho_l=1.3, rho_g=0.2, amp=0.0, K=0,
+               gravity=g, rho0=1.0, tuned=False)
+    J0 = s.totals()[1:1 + len(g)]
+    s.step(50)
+    J = s.totals()[1:1 + len(g)]
+    expect = J0 + 50 * nx * ny * nz * 0.3 * np.asarray(g)
+    assert np.allclose(J, expect, rtol=1e-4, atol=1e-9), (J, expect)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_gravity_tiles_and_variants_bitwise_equal(q):
+    spec = (W.two_bubble(gap=3, nx=150, ny=90, radius=12.0) if q == 9 else
+            W.SimSpec(name="spheres", q=19, nx=44, ny=24, nz=24, tau=0.9, G=-5.0, rho_l=1.93,
+                      rho_g=0.16, amp=1e-3, seed=3, K=10, steps=30,
+                      centres=np.array([(10.5, 11.5, 11.5), (29.5, 11.5, 11.5)]),
+                      radii=np.array([7.0, 7.0]), budgets=np.zeros(2), rate=0.0))
+    g = (0.0, -3e-5) if q == 9 else (0.0, 2e-5, -3e-5)
+    shapes = ([(64, 1, 3, 1), (128, 1, 8, 3), (256, 1, 64, 1)] if q == 9 else
+              [(32, 4, 5, 1), (64, 8, 16, 3), (256, 4, 64, 3)])
+    ref = None
+    for tx, ty, tz, v in shapes:
+        s = gpu_from_spec(spec, gravity=g, tile=(tx, ty, tz), variant=v)
+        s.step(30)
+        f = s.get_populations()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), (tx, ty, tz, v)
+        s.close()

@@ -90,8 +90,9 @@ typedef struct sc_params {
      * every bubble owns its gas nodes and `corona` liquid layers around them (grown by lattice
      * neighbours, ties to the smaller id); in the force a neighbour owned by a different bubble
      * that the criterion has not merged with the node's contributes psi(rho_liquid) instead of
-     * its own psi.  Owners are rebuilt at every test pass after its merges.  FP32 storage only
-     * (SC_E_UNSUPPORTED otherwise, and with step_variant 2); at most 65534 nuclei. */
+     * its own psi.  Owners are rebuilt at every test pass after its merges; only the nodes next
+     * to another bubble's node are affected, and they are re-stepped by a fix-up kernel after
+     * every step.  FP32 storage only (SC_E_UNSUPPORTED otherwise); at most 65534 nuclei. */
     int32_t barrier;           /* 0 off (default), 1 on */
     int32_t corona;            /* liquid layers a bubble owns, 0..64 (default 3) */
     /* Gravity for drainage studies (the paper's runs leave it out): a body force

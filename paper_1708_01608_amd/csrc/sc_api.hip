@@ -65,8 +65,9 @@ struct sc_sim {
 
     // modified Shan-Chen barrier: owner id per node (uint16, fixed address for the step
     // kernel), a second buffer for the corona layers, and the owner id of each bubble slot
-    DevBuf owner, owner2, owner_ids;
+    DevBuf owner, owner2, owner_ids, frontier;
     double psi_l = 0.0;
+    int frontier_count = 0;  // frontier nodes the barrier fix-up re-steps after each step
 
     // gravity: buoyancy reference density (the mean density when rho_buoyancy <= 0)
     bool grav = false;
@@ -418,7 +419,9 @@ int totals_now(sc_sim* s, double out[4])
 // bubble's gas nodes carry 1 + the smallest nucleus index of the criterion-merged groups of its
 // nuclei, then `corona` layers grow into the liquid, a free node taking the smallest id among
 // its lattice neighbours.  The layers alternate between two buffers and the seed goes to the one
-// that makes the last layer land in s->owner, whose address the step kernel keeps.
+// that makes the last layer land in s->owner, whose address the kernels keep.  Then the frontier
+// nodes (owned, next to another bubble's node: the only ones whose force the barrier changes)
+// are listed for the fix-up that follows every step until the next pass.
 int build_owner(sc_sim* s, int nb)
 {
     const FieldArgs fa = field_args(s);
@@ -448,6 +451,18 @@ int build_owner(sc_sim* s, int nb)
         HIPX(launch_owner_grow(s->q, bufs[cur], bufs[cur ^ 1], fa, s->stream));
         cur ^= 1;
     }
+    s->frontier_count = 0;
+    if (nb < 2) return SC_OK;  // one bubble or none: no node can see another bubble
+    TRY(ensure(s, s->frontier, sizeof(uint32_t) * (size_t)s->N));
+    TRY(ensure(s, s->small, 4096));
+    unsigned int* cnt_d = (unsigned int*)((char*)s->small.p + 192);
+    HIPX(launch_fill_i32((int32_t*)cnt_d, 0, 1, s->stream));
+    HIPX(launch_frontier_list(s->q, (const uint16_t*)s->owner.p, (uint32_t*)s->frontier.p, cnt_d,
+                              fa, s->stream));
+    unsigned int got = 0;
+    HIPX(hipMemcpyAsync(&got, cnt_d, sizeof(got), hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    s->frontier_count = (int)got;
     return SC_OK;
 }
 
@@ -733,8 +748,6 @@ int validate(const sc_params* p)
         return fail(SC_E_INVAL, "corona must be in [0, 64]");
     if (p->barrier && p->storage != SC_STORE_F32)
         return fail(SC_E_UNSUPPORTED, "the barrier is offered on FP32 storage only");
-    if (p->barrier && p->step_variant == 2)
-        return fail(SC_E_UNSUPPORTED, "the barrier has no software-pipelined kernel");
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(p->gravity[c])) return fail(SC_E_INVAL, "gravity must be finite");
     if (!std::isfinite(p->rho_buoyancy)) return fail(SC_E_INVAL, "rho_buoyancy must be finite");
@@ -762,7 +775,7 @@ void release(sc_sim* s)
                       &s->u_out, &s->p_out, &s->lap_out, &s->partials, &s->small, &s->tmp64,
                       &s->mask8, &s->nodes, &s->list_node, &s->list_slot, &s->add_tab,
                       &s->pair_buf, &s->res_buf, &s->bub_tab, &s->owner, &s->owner2,
-                      &s->owner_ids})
+                      &s->owner_ids, &s->frontier})
         dev_free(s, b->p);
     dev_free(s, s->f[0]);
     dev_free(s, s->f[1]);
@@ -833,8 +846,8 @@ int sc_create(const sc_params* p, sc_sim** out)
     s->grav = p->gravity[0] != 0.0 || p->gravity[1] != 0.0 ||
               (p->lattice == SC_D3Q19 && p->gravity[2] != 0.0);
     if (p->lattice == SC_D2Q9) s->p.gravity[2] = 0.0;
-    // a tuned pipelined shape runs as the plain non-temporal variant of the extended kernels
-    if ((p->barrier || s->grav) && s->shape.variant == 2) s->shape.variant = 3;
+    // a tuned pipelined shape runs as the plain non-temporal variant of the gravity kernels
+    if (s->grav && s->shape.variant == 2) s->shape.variant = 3;
     s->psi_l = 1.0 - std::exp(-p->rho_liquid);
     if (p->stream) {
         s->stream = (hipStream_t)p->stream;
@@ -944,6 +957,10 @@ int sc_step(sc_sim* s, int32_t nsteps)
         TRY(prof_begin(s, SC_KERNEL_STEP, &pe));
         HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a,
                          s->shape, s->stream));
+        if (s->p.barrier && s->frontier_count > 0)
+            HIPX(launch_barrier_fix(s->q, s->p.storage, s->compute, s->f[s->cur],
+                                    s->f[s->cur ^ 1], a, (const uint32_t*)s->frontier.p,
+                                    s->frontier_count, s->stream));
         TRY(prof_end(s, pe));
         s->cur ^= 1;
         // blowing-agent source after streaming
@@ -1233,7 +1250,7 @@ int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int3
     int rc = SC_OK;
     for (const StepShape& sh : cand) {
         if (!step_shape_supported(s->q, sh)) continue;
-        if (s->p.barrier && sh.variant == 2) continue;  // no pipelined barrier kernel
+        if (s->grav && sh.variant == 2) continue;  // no pipelined gravity kernel
         a.planes = sh.tile_z;
         // one untimed launch, then `trials` timed launches current -> spare buffer
         hipError_t e = launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1],

@@ -44,6 +44,9 @@ bool step_shape_supported(int q, const StepShape& s);
 bool step_combo_supported(int storage, int compute);
 hipError_t launch_step(int q, int storage, int compute, const void* src, void* dst,
                        const StepArgs& a, const StepShape& s, hipStream_t st);
+// Barrier fix-up of the listed frontier nodes after a step (same src/dst as that step).
+hipError_t launch_barrier_fix(int q, int storage, int compute, const void* src, void* dst,
+                              const StepArgs& a, const uint32_t* list, int count, hipStream_t st);
 
 // --- state kernels (sc_step.hip) -----------------------------------------------------------
 struct InitArgs {
@@ -141,6 +144,9 @@ hipError_t launch_owner_seed(const uint32_t* labels, const int32_t* slot_of_root
                              hipStream_t st);
 hipError_t launch_owner_grow(int q, const uint16_t* in, uint16_t* out, const FieldArgs& a,
                              hipStream_t st);
+// Frontier nodes (owned, with a lattice neighbour of a different owner) appended to list.
+hipError_t launch_frontier_list(int q, const uint16_t* owner, uint32_t* list,
+                                unsigned int* count_d, const FieldArgs& a, hipStream_t st);
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n,

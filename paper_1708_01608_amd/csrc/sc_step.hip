@@ -16,6 +16,7 @@
 // tile's own populations stay in registers for the collision one iteration later, the ring
 // nodes' populations are loaded only to form their psi.  Four LDS plane slots let one barrier
 // per plane separate writers from readers.
+#include <algorithm>
 #include <type_traits>
 
 #include "sc_device.hpp"
@@ -51,10 +52,6 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
 {
     using L = lat<9>;
     __shared__ A ps[4][TX + 2];
-    __shared__ uint16_t po[EXT ? 4 : 1][EXT ? TX + 2 : 1];  // owners beside psi (barrier)
-    // extended kernels: barrier when an owner field is given, gravity when c.grav
-    const uint16_t* __restrict__ ownr = a.owner;
-    const bool bar = EXT && ownr != nullptr;
     const Coef<A> c = coef_of(a, A());
     const int nx = a.nx, ny = a.ny;
     const int64_t N = a.N;
@@ -85,13 +82,11 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
             float g[9];
             pull_node<9>(src, N, nx, ny, x, xm, xp, y, ym, yp, 0, 0, 0, g);
             ps[0][tx + 1] = psi_f(c.rho_ref + sum_dev<9, A>(g));
-            if constexpr (EXT) if (bar) po[0][tx + 1] = ownr[x + (int64_t)nx * y];
         }
         if (ring) {
             float h[9];
             pull_node<9>(src, N, nx, ny, hx, hxm, hxp, y, ym, yp, 0, 0, 0, h);
             ps[0][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
-            if constexpr (EXT) if (bar) po[0][hl] = ownr[hx + (int64_t)nx * y];
         }
     }
     {
@@ -101,13 +96,11 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
             pull_node<9>(src, N, nx, ny, x, xm, xp, y, ym, yp, 0, 0, 0, cur);
             dcur = sum_dev<9, A>(cur);
             ps[1][tx + 1] = psi_f(c.rho_ref + dcur);
-            if constexpr (EXT) if (bar) po[1][tx + 1] = ownr[x + (int64_t)nx * y];
         }
         if (ring) {
             float h[9];
             pull_node<9>(src, N, nx, ny, hx, hxm, hxp, y, ym, yp, 0, 0, 0, h);
             ps[1][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
-            if constexpr (EXT) if (bar) po[1][hl] = ownr[hx + (int64_t)nx * y];
         }
     }
 
@@ -121,28 +114,21 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
                 pull_node<9>(src, N, nx, ny, x, xm, xp, yn, ym, yp, 0, 0, 0, nxt);
                 dnxt = sum_dev<9, A>(nxt);
                 ps[sn][tx + 1] = psi_f(c.rho_ref + dnxt);
-                if constexpr (EXT) if (bar) po[sn][tx + 1] = ownr[x + (int64_t)nx * yn];
             }
             if (ring) {
                 float h[9];
                 pull_node<9>(src, N, nx, ny, hx, hxm, hxp, yn, ym, yp, 0, 0, 0, h);
                 ps[sn][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
-                if constexpr (EXT) if (bar) po[sn][hl] = ownr[hx + (int64_t)nx * yn];
             }
         }
         __syncthreads();
         if (own) {
             const A pc = ps[s][tx + 1];
-            uint16_t oc = 0;
-            if constexpr (EXT) if (bar) oc = po[s][tx + 1];
             A fx = (A)0, fy = (A)0;
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 const int slot = L::ey[i] > 0 ? sn : (L::ey[i] < 0 ? sp : s);
-                A psn = ps[slot][tx + 1 + L::ex[i]];
-                if constexpr (EXT)
-                    if (bar) psn = seen_psi<true>(psn, oc, po[slot][tx + 1 + L::ex[i]], c.psi_l);
-                const A pn = weight<9, A>(i) * psn;
+                const A pn = weight<9, A>(i) * ps[slot][tx + 1 + L::ex[i]];
                 if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
                 if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
             }
@@ -165,10 +151,6 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
 {
     using L = lat<19>;
     __shared__ A ps[4][TY + 2][TX + 2];
-    __shared__ uint16_t po[EXT ? 4 : 1][EXT ? TY + 2 : 1][EXT ? TX + 2 : 1];  // owners (barrier)
-    // extended kernels: barrier when an owner field is given, gravity when c.grav
-    const uint16_t* __restrict__ ownr = a.owner;
-    const bool bar = EXT && ownr != nullptr;
     const Coef<A> c = coef_of(a, A());
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t N = a.N;
@@ -214,15 +196,11 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
             float g[19];
             pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z, zm, zp, g);
             ps[0][ty + 1][tx + 1] = psi_f(c.rho_ref + sum_dev<19, A>(g));
-            if constexpr (EXT)
-                if (bar) po[0][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * z)];
         }
         if (ring) {
             float h[19];
             pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z, zm, zp, h);
             ps[0][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
-            if constexpr (EXT)
-                if (bar) po[0][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * z)];
         }
     }
     {
@@ -232,15 +210,11 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
             pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z, zm, zp, cur);
             dcur = sum_dev<19, A>(cur);
             ps[1][ty + 1][tx + 1] = psi_f(c.rho_ref + dcur);
-            if constexpr (EXT)
-                if (bar) po[1][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * z)];
         }
         if (ring) {
             float h[19];
             pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z, zm, zp, h);
             ps[1][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
-            if constexpr (EXT)
-                if (bar) po[1][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * z)];
         }
     }
 
@@ -254,34 +228,21 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
                 pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, zn, zm, zp, nxt);
                 dnxt = sum_dev<19, A>(nxt);
                 ps[sn][ty + 1][tx + 1] = psi_f(c.rho_ref + dnxt);
-                if constexpr (EXT)
-                    if (bar)
-                        po[sn][ty + 1][tx + 1] = ownr[x + (int64_t)nx * (y + (int64_t)ny * zn)];
             }
             if (ring) {
                 float h[19];
                 pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, zn, zm, zp, h);
                 ps[sn][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
-                if constexpr (EXT)
-                    if (bar)
-                        po[sn][hly][hlx] = ownr[hx + (int64_t)nx * (hy + (int64_t)ny * zn)];
             }
         }
         __syncthreads();
         if (own) {
             const A pc = ps[s][ty + 1][tx + 1];
-            uint16_t oc = 0;
-            if constexpr (EXT) if (bar) oc = po[s][ty + 1][tx + 1];
             A fx = (A)0, fy = (A)0, fz = (A)0;
 #pragma unroll
             for (int i = 1; i < 19; ++i) {
                 const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
-                A psn = ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
-                if constexpr (EXT)
-                    if (bar)
-                        psn = seen_psi<true>(
-                            psn, oc, po[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]], c.psi_l);
-                const A pn = weight<19, A>(i) * psn;
+                const A pn = weight<19, A>(i) * ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
                 if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
                 if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
                 if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
@@ -421,6 +382,86 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
 }
 
 // ------------------------------------------------------------------------------------------
+// Barrier fix-up (modified Shan-Chen, Sec. 3.1): after the marching kernel has stepped every
+// node with the plain force, the frontier nodes -- owned nodes next to a node of another,
+// un-merged bubble, listed by the test pass -- are stepped again from the same source with the
+// neighbours of that other bubble seen as bulk liquid, psi(rho_l), and overwrite their outputs.
+// Same operations in the same order as the marching kernel, so only the substitution differs,
+// and the result does not depend on the marching kernel's tile.
+// ------------------------------------------------------------------------------------------
+template <int Q, typename S, typename A, bool EXT>
+__global__ void __launch_bounds__(256) k_barrier_fix(const S* __restrict__ src,
+                                                     S* __restrict__ dst, StepArgs a,
+                                                     const uint32_t* __restrict__ list, int count)
+{
+    using L = lat<Q>;
+    const Coef<A> c = coef_of(a, A());
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t N = a.N;
+    const uint16_t* __restrict__ ownr = a.owner;
+    auto pull = [&](int x, int y, int z, float* g) {
+        pull_node<Q>(src, N, nx, ny, x, wrap_once(x - 1, nx), wrap_once(x + 1, nx), y,
+                     wrap_once(y - 1, ny), wrap_once(y + 1, ny), z,
+                     Q == 19 ? wrap_once(z - 1, nz) : 0, Q == 19 ? wrap_once(z + 1, nz) : 0, g);
+    };
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
+        const uint32_t n = list[k];
+        const int x = (int)(n % (uint32_t)nx);
+        const uint32_t r = n / (uint32_t)nx;
+        const int y = (int)(r % (uint32_t)ny), z = (int)(r / (uint32_t)ny);
+        float g[Q];
+        pull(x, y, z, g);
+        const A drho = sum_dev<Q, A>(g);
+        const A pc = psi_f(c.rho_ref + drho);
+        const uint16_t o = ownr[n];
+        A fx = (A)0, fy = (A)0, fz = (A)0;
+#pragma unroll 1
+        for (int i = 1; i < Q; ++i) {
+            const int xx = wrap_once(x + L::ex[i], nx), yy = wrap_once(y + L::ey[i], ny);
+            const int zz = Q == 19 ? wrap_once(z + L::ez[i], nz) : 0;
+            const uint16_t on = ownr[xx + (int64_t)nx * (yy + (int64_t)ny * zz)];
+            A psn;
+            if (o != 0 && on != 0 && on != o) {
+                psn = c.psi_l;
+            } else {
+                float h[Q];
+                pull(xx, yy, zz, h);
+                psn = psi_f(c.rho_ref + sum_dev<Q, A>(h));
+            }
+            const A pn = weight<Q, A>(i) * psn;
+            if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
+            if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
+            if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
+        }
+        const A gp = -c.G * pc;
+        collide_store<Q, A, S, false, EXT>(dst, N, n, g, drho, gp * fx, gp * fy,
+                                           Q == 19 ? gp * fz : (A)0, c);
+    }
+}
+
+hipError_t launch_barrier_fix(int q, int storage, int compute, const void* src, void* dst,
+                              const StepArgs& a, const uint32_t* list, int count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (storage != SC_STORE_F32 || !a.owner) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)std::min(65535, (count + 255) / 256)), block(256);
+    const float* s = (const float*)src;
+    float* d = (float*)dst;
+#define SC_FIX(QQ, AA, EE) \
+    hipLaunchKernelGGL((k_barrier_fix<QQ, float, AA, EE>), grid, block, 0, st, s, d, a, list, count)
+    const bool g = a.grav != 0;
+    if (compute == SC_COMPUTE_F64) {
+        if (q == 9) { if (g) SC_FIX(9, double, true); else SC_FIX(9, double, false); }
+        else { if (g) SC_FIX(19, double, true); else SC_FIX(19, double, false); }
+    } else {
+        if (q == 9) { if (g) SC_FIX(9, float, true); else SC_FIX(9, float, false); }
+        else { if (g) SC_FIX(19, float, true); else SC_FIX(19, float, false); }
+    }
+#undef SC_FIX
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 // Launch
 // ------------------------------------------------------------------------------------------
 bool step_shape_supported(int q, const StepShape& s)
@@ -457,10 +498,10 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
     const int nb = g.gx * g.gy * g.gz;
     g.remap = (nb % 8 == 0) ? 1 : 0;
     dim3 grid(nb);
-    // the extended kernels (barrier and/or gravity) exist for FP32 storage (either arithmetic),
-    // marching variants only
+    // the extended kernels (gravity) exist for FP32 storage (either arithmetic), marching
+    // variants only
     constexpr bool kBarOK = std::is_same<S, float>::value;
-    const bool ext = a.owner != nullptr || a.grav != 0;
+    const bool ext = a.grav != 0;
     if (ext && (!kBarOK || s.variant == 2)) return hipErrorInvalidValue;
 #define SC_L2(TX)                                                                                \
     if (s.tile_x == TX) {                                                                        \

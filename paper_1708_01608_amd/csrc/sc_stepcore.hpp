@@ -58,14 +58,6 @@ __device__ __forceinline__ Coef<double> coef_of(const StepArgs& a, double)
                         a.gd[0], a.gd[1], a.gd[2], a.rho0d, a.grav};
 }
 
-// psi a node with owner oc sees at a neighbour with owner on: bulk liquid where the neighbour
-// belongs to a different bubble that has not merged with the node's (both ids nonzero).
-template <bool BAR, typename A>
-__device__ __forceinline__ A seen_psi(A psi_n, uint16_t oc, uint16_t on, A psi_l)
-{
-    if (BAR && oc != 0 && on != 0 && on != oc) return psi_l;
-    return psi_n;
-}
 
 // Forced BGK collision on deviations g_i = f_i - w_i rho_ref; writes f_i* - w_i rho_ref.
 // With h_i = g_i - w_i drho (one fused rounding), the relaxation

@@ -494,6 +494,28 @@ __global__ void k_owner_grow(const uint16_t* in, uint16_t* out, FieldArgs a)
     }
 }
 
+// Frontier nodes: owned nodes with a lattice neighbour owned by a different bubble (the only
+// nodes whose force the barrier changes), appended in any order.
+template <int Q>
+__global__ void k_frontier_list(const uint16_t* owner, uint32_t* list, unsigned int* count,
+                                FieldArgs a)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const uint16_t o = owner[n];
+        if (o == 0) continue;
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+        bool frontier = false;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const uint16_t v = owner[shifted<Q>(x, y, z, i, +1, a)];
+            if (v != 0 && v != o) frontier = true;
+        }
+        if (frontier) list[atomicAdd(count, 1u)] = (uint32_t)n;
+    }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n)
 {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
@@ -672,6 +694,20 @@ hipError_t launch_owner_seed(const uint32_t* labels, const int32_t* slot_of_root
 {
     hipLaunchKernelGGL(k_owner_seed, grid_for(N), dim3(256), 0, st, labels, slot_of_root, ids_d,
                        nb, owner, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_frontier_list(int q, const uint16_t* owner, uint32_t* list,
+                                unsigned int* count_d, const FieldArgs& a, hipStream_t st)
+{
+    if (q == 9)
+        hipLaunchKernelGGL((k_frontier_list<9>), grid_for(a.N), dim3(256), 0, st, owner, list,
+                           count_d, a);
+    else if (q == 19)
+        hipLaunchKernelGGL((k_frontier_list<19>), grid_for(a.N), dim3(256), 0, st, owner, list,
+                           count_d, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

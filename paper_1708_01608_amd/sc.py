@@ -252,8 +252,8 @@ class Sim:
         comp_name = compute if isinstance(compute, str) else {0: "auto", 1: "f32", 2: "f64"}[compute]
         if tile is None and tuned:
             tile, variant = _tuned_shape(q, nx, ny, nz, storage, comp_name, variant)
-            if (barrier or gravity is not None) and variant == 2:
-                variant = 3  # no pipelined extended kernel: same tile, plain variant
+            if gravity is not None and any(gravity) and variant == 2:
+                variant = 3  # no pipelined gravity kernel: same tile, plain variant
         if tile is not None:
             p.tile_x, p.tile_y, p.tile_z = tile
         p.step_variant = int(variant)

@@ -94,15 +94,13 @@ def test_invalid_parameters_are_rejected_before_any_device_work(lib, field, valu
 
 @pytest.mark.parametrize("field,value,code", [
     ("corona", -1, sc.SC_E_INVAL), ("corona", 65, sc.SC_E_INVAL), ("barrier", 2, sc.SC_E_INVAL),
-    ("storage", 1, sc.SC_E_UNSUPPORTED), ("step_variant", 2, sc.SC_E_UNSUPPORTED),
+    ("storage", 1, sc.SC_E_UNSUPPORTED),
 ])
 def test_barrier_parameters_are_checked(lib, field, value, code):
     p = sc.Params()
     lib.sc_params_init(C.byref(p))
     assert p.barrier == 0 and p.corona == 3
     p.barrier = 1
-    if field == "step_variant":
-        p.lattice, p.nz, p.tile_x, p.tile_y, p.tile_z = 19, 16, 32, 8, 16
     setattr(p, field, value)
     h = C.c_void_p()
     assert lib.sc_create(C.byref(p), C.byref(h)) == code

@@ -104,7 +104,7 @@ def test_barrier_invisible_while_apart_on_gpu():
 def test_barrier_tiles_and_variants_bitwise_equal(q):
     spec = W.two_bubble(gap=3, nx=150, ny=90, radius=12.0) if q == 9 else _spheres(gap=3)
     shapes = ([(64, 1, 3, 1), (128, 1, 8, 3), (256, 1, 64, 1)] if q == 9 else
-              [(32, 4, 5, 1), (64, 8, 16, 3), (256, 4, 64, 3), (16, 16, 7, 1)])
+              [(32, 4, 5, 1), (64, 8, 16, 3), (256, 4, 64, 3), (16, 16, 7, 2)])
     ref = None
     for tx, ty, tz, v in shapes:
         g = gpu_from_spec(spec, barrier=True, tile=(tx, ty, tz), variant=v)

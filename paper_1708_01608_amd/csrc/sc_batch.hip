@@ -166,15 +166,14 @@ __device__ void batch_step(const float* __restrict__ src, float* __restrict__ ds
                 const int ru = row[r] + 1 < rb ? rc + nx : sn;
                 const int rd = row[r] > 0 ? rc - nx : sp + (rb - 1) * nx;
                 const A pc = ps[rc + col[r]];
-                A fx = (A)0, fy = (A)0;  // same order as the single-box kernel
-#pragma unroll
-                for (int i = 1; i < 9; ++i) {
-                    const int rw = L::ey[i] > 0 ? ru : (L::ey[i] < 0 ? rd : rc);
-                    const int xx = L::ex[i] > 0 ? xp[r] : (L::ex[i] < 0 ? xm[r] : col[r]);
-                    const A pn = weight<9, A>(i) * ps[rw + xx];
-                    if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
-                    if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
-                }
+                A fx, fy, fz;  // the single-box kernel's grouped sum
+                interaction_sum<9, A>(
+                    [&](int i) {
+                        const int rw = L::ey[i] > 0 ? ru : (L::ey[i] < 0 ? rd : rc);
+                        const int xx = L::ex[i] > 0 ? xp[r] : (L::ex[i] < 0 ? xm[r] : col[r]);
+                        return ps[rw + xx];
+                    },
+                    fx, fy, fz);
                 const A gp = -c.G * pc;
                 collide_store<9, A, float>(dst, N, (uint32_t)(col[r] + nx * y), cur[r], dcur[r],
                                            gp * fx, gp * fy, (A)0, c);

@@ -124,14 +124,13 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
         __syncthreads();
         if (own) {
             const A pc = ps[s][tx + 1];
-            A fx = (A)0, fy = (A)0;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const int slot = L::ey[i] > 0 ? sn : (L::ey[i] < 0 ? sp : s);
-                const A pn = weight<9, A>(i) * ps[slot][tx + 1 + L::ex[i]];
-                if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
-                if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
-            }
+            A fx, fy, fz;
+            interaction_sum<9, A>(
+                [&](int i) {
+                    const int slot = L::ey[i] > 0 ? sn : (L::ey[i] < 0 ? sp : s);
+                    return ps[slot][tx + 1 + L::ex[i]];
+                },
+                fx, fy, fz);
             const A gp = -c.G * pc;
             collide_store<9, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * y), cur, dcur, gp * fx,
                                        gp * fy, (A)0, c);
@@ -238,15 +237,13 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
         __syncthreads();
         if (own) {
             const A pc = ps[s][ty + 1][tx + 1];
-            A fx = (A)0, fy = (A)0, fz = (A)0;
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
-                const A pn = weight<19, A>(i) * ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
-                if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
-                if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
-                if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
-            }
+            A fx, fy, fz;
+            interaction_sum<19, A>(
+                [&](int i) {
+                    const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
+                    return ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
+                },
+                fx, fy, fz);
             const A gp = -c.G * pc;
             collide_store<19, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
                                         gp * fx, gp * fy, gp * fz, c);
@@ -349,15 +346,13 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
         }
         if (own) {
             const A pc = ps[s][ty + 1][tx + 1];
-            A fx = (A)0, fy = (A)0, fz = (A)0;
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
-                const A pn = weight<19, A>(i) * ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
-                if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
-                if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
-                if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
-            }
+            A fx, fy, fz;
+            interaction_sum<19, A>(
+                [&](int i) {
+                    const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
+                    return ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
+                },
+                fx, fy, fz);
             const A gp = -c.G * pc;
             collide_store<19, A, S>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
                                     gp * fx, gp * fy, gp * fz, c);
@@ -414,25 +409,18 @@ __global__ void __launch_bounds__(256) k_barrier_fix(const S* __restrict__ src,
         const A drho = sum_dev<Q, A>(g);
         const A pc = psi_f(c.rho_ref + drho);
         const uint16_t o = ownr[n];
-        A fx = (A)0, fy = (A)0, fz = (A)0;
-#pragma unroll 1
-        for (int i = 1; i < Q; ++i) {
-            const int xx = wrap_once(x + L::ex[i], nx), yy = wrap_once(y + L::ey[i], ny);
-            const int zz = Q == 19 ? wrap_once(z + L::ez[i], nz) : 0;
-            const uint16_t on = ownr[xx + (int64_t)nx * (yy + (int64_t)ny * zz)];
-            A psn;
-            if (o != 0 && on != 0 && on != o) {
-                psn = c.psi_l;
-            } else {
+        A fx, fy, fz;
+        interaction_sum<Q, A>(
+            [&](int i) -> A {
+                const int xx = wrap_once(x + L::ex[i], nx), yy = wrap_once(y + L::ey[i], ny);
+                const int zz = Q == 19 ? wrap_once(z + L::ez[i], nz) : 0;
+                const uint16_t on = ownr[xx + (int64_t)nx * (yy + (int64_t)ny * zz)];
+                if (o != 0 && on != 0 && on != o) return c.psi_l;  // another bubble's lattice
                 float h[Q];
                 pull(xx, yy, zz, h);
-                psn = psi_f(c.rho_ref + sum_dev<Q, A>(h));
-            }
-            const A pn = weight<Q, A>(i) * psn;
-            if (L::ex[i] > 0) fx += pn; else if (L::ex[i] < 0) fx -= pn;
-            if (L::ey[i] > 0) fy += pn; else if (L::ey[i] < 0) fy -= pn;
-            if (L::ez[i] > 0) fz += pn; else if (L::ez[i] < 0) fz -= pn;
-        }
+                return psi_f(c.rho_ref + sum_dev<Q, A>(h));
+            },
+            fx, fy, fz);
         const A gp = -c.G * pc;
         collide_store<Q, A, S, false, EXT>(dst, N, n, g, drho, gp * fx, gp * fy,
                                            Q == 19 ? gp * fz : (A)0, c);

@@ -29,6 +29,58 @@ __device__ __forceinline__ void pull_node(const S* __restrict__ src, int64_t N, 
     }
 }
 
+// Index of the lattice velocity (dx, dy, dz) in lat<Q> (compile time).
+template <int Q>
+__device__ __host__ constexpr int dir_of(int dx, int dy, int dz)
+{
+    for (int i = 0; i < Q; ++i)
+        if (lat<Q>::ex[i] == dx && lat<Q>::ey[i] == dy && lat<Q>::ez[i] == dz) return i;
+    return -1;
+}
+
+// Interaction sum S = sum_{i != 0} w_i psi(x + e_i) e_i (the Shan-Chen force is -G psi(x) S),
+// grouped by the lattice's symmetry: opposite axis neighbours enter as one difference, and the
+// four diagonals of each coordinate plane as two differences that the plane's two components
+// share (a1 = psi(+x+y) - psi(-x-y) counts for +x and +y, a2 = psi(+x-y) - psi(-x+y) for +x and
+// -y).  24 operations in D3Q19 and 10 in D2Q9, against 48 and 20 for the plain sum.  psi(i)
+// returns the pseudopotential seen at neighbour i; every direction is asked once.
+template <int Q, typename A, typename P>
+__device__ __forceinline__ void interaction_sum(P psi, A& sx, A& sy, A& sz)
+{
+    constexpr int E = dir_of<Q>(1, 0, 0), W = dir_of<Q>(-1, 0, 0);
+    constexpr int N = dir_of<Q>(0, 1, 0), S = dir_of<Q>(0, -1, 0);
+    const A w1 = weight<Q, A>(E), w2 = weight<Q, A>(dir_of<Q>(1, 1, 0));
+    const A a1 = psi(dir_of<Q>(1, 1, 0)) - psi(dir_of<Q>(-1, -1, 0));
+    const A a2 = psi(dir_of<Q>(1, -1, 0)) - psi(dir_of<Q>(-1, 1, 0));
+    if constexpr (Q == 9) {
+        sx = fmad(w1, psi(E) - psi(W), w2 * (a1 + a2));
+        sy = fmad(w1, psi(N) - psi(S), w2 * (a1 - a2));
+        sz = (A)0;
+    } else {
+        constexpr int T = dir_of<Q>(0, 0, 1), B = dir_of<Q>(0, 0, -1);
+        const A b1 = psi(dir_of<Q>(1, 0, 1)) - psi(dir_of<Q>(-1, 0, -1));
+        const A b2 = psi(dir_of<Q>(1, 0, -1)) - psi(dir_of<Q>(-1, 0, 1));
+        const A c1 = psi(dir_of<Q>(0, 1, 1)) - psi(dir_of<Q>(0, -1, -1));
+        const A c2 = psi(dir_of<Q>(0, 1, -1)) - psi(dir_of<Q>(0, -1, 1));
+        sx = fmad(w1, psi(E) - psi(W), w2 * ((a1 + a2) + (b1 + b2)));
+        sy = fmad(w1, psi(N) - psi(S), w2 * ((a1 - a2) + (c1 + c2)));
+        sz = fmad(w1, psi(T) - psi(B), w2 * ((b1 - b2) + (c1 - c2)));
+    }
+}
+
+// 1/rho: FP64 through the hardware reciprocal and two Newton steps (each doubles the correct
+// bits: a faithful result for the densities here, at half the cost of IEEE division); FP32 as
+// the compiler divides.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+
 // Deviation sum sum_i g_i in the arithmetic type A (fixed order: the ring and the owner of a
 // node obtain the same value).
 template <int Q, typename A>
@@ -117,7 +169,7 @@ __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, ui
         if (L::ey[i] > 0) jy += (A)g[i]; else if (L::ey[i] < 0) jy -= (A)g[i];
         if (L::ez[i] > 0) jz += (A)g[i]; else if (L::ez[i] < 0) jz -= (A)g[i];
     }
-    const A inv = (A)1 / rho;
+    const A inv = recip(rho);
     // velocity-shift forcing: u_eq = (j + tau F) / rho
     const A ux = fmad(c.tau, Fx, jx) * inv;
     const A uy = fmad(c.tau, Fy, jy) * inv;

@@ -73,6 +73,8 @@ def _load():
     lib.orc_uniform.argtypes = [C.c_uint64, C.c_uint64]
     lib.orc_splitmix64.restype = C.c_uint64
     lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_film_geometry.restype = C.c_int
+    lib.orc_film_geometry.argtypes = [P, C.c_int, C.c_int, P, P, P]
     lib.orc_set_gravity.restype = C.c_int
     lib.orc_set_gravity.argtypes = [P, P, C.c_double]
     lib.orc_rho0.restype = C.c_double
@@ -170,6 +172,15 @@ class OracleSim:
     def set_barrier(self, on, corona=3):
         if self._lib.orc_set_barrier(self._h, 1 if on else 0, int(corona)) != 0:
             raise ValueError("corona must be >= 0")
+
+    def film_geometry(self, a, b):
+        """(h, R_d, n_lines) of the bubbles holding nuclei a and b at the last test pass."""
+        h, r, n = C.c_double(), C.c_double(), C.c_int()
+        rc = self._lib.orc_film_geometry(self._h, int(a), int(b), C.byref(h), C.byref(r),
+                                         C.byref(n))
+        if rc != 0:
+            raise ValueError(f"orc_film_geometry returned {rc}")
+        return h.value, r.value, n.value
 
     def set_gravity(self, g, rho0=0.0):
         gg = np.zeros(3)

@@ -785,6 +785,124 @@ static int test_pass(orc_sim* s, int with_criterion)
 
 int orc_test_pass(orc_sim* s) { return test_pass(s, 1); }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Film geometry of a bubble pair (Sec. 3: the film is a disc of radius R_d and thickness h   */
+/* between two interfaces; Sec. 4, Fig. 3: h_c against R_d, R_d against R_b at rupture).       */
+/* ------------------------------------------------------------------------------------------ */
+/* One line parallel to the centroid segment, shifted by off: walk the T+1 samples rounded to
+ * nodes (consecutive repeats dropped), find the last node of A and the first node of B after it.
+ * Returns the film length (liquid nodes strictly between), or 0 if the line does not cross a
+ * film of 1..film_max liquid nodes free of other labels.  Walk nodes and their unwrapped
+ * positions go to nodes/pos (capacity T+1) when given; *sa_out, *sb_out get the run ends. */
+static int film_line(const orc_sim* s, const double cen[3], const double off[3],
+                     const double dv[3], int T, uint32_t la, uint32_t lb, int64_t* nodes,
+                     double (*pos)[3], int* sa_out, int* sb_out)
+{
+    int64_t prev = -1;
+    int nw = 0, sa = -1, sb = -1;
+    int64_t* wn = (int64_t*)malloc(sizeof(int64_t) * (size_t)(T + 1));
+    double(*wp)[3] = (double(*)[3])malloc(sizeof(double) * 3 * (size_t)(T + 1));
+    for (int k = 0; k <= T; ++k) {
+        double q[3], r[3];
+        for (int a = 0; a < 3; ++a) {
+            q[a] = cen[a] + off[a] + dv[a] * (double)k / (double)T;
+            r[a] = floor(q[a] + 0.5);
+        }
+        if (s->L.d == 2) r[2] = 0.0;
+        int64_t node = node_index(s, wrap((int)r[0], s->nx), wrap((int)r[1], s->ny),
+                                  s->L.d == 3 ? wrap((int)r[2], s->nz) : 0);
+        if (node == prev) continue;
+        prev = node;
+        wn[nw] = node;
+        for (int a = 0; a < 3; ++a) wp[nw][a] = r[a];
+        ++nw;
+    }
+    for (int k = 0; k < nw; ++k)
+        if (s->labels[wn[k]] == la) sa = k;
+    if (sa >= 0)
+        for (int k = sa + 1; k < nw; ++k)
+            if (s->labels[wn[k]] == lb) { sb = k; break; }
+    int len = (sa >= 0 && sb >= 0) ? sb - sa - 1 : 0;
+    for (int k = sa + 1; len > 0 && k < sb; ++k)
+        if (s->labels[wn[k]] != 0) len = 0;
+    if (len > s->film_max) len = 0;
+    if (nodes) for (int k = 0; k < nw; ++k) { nodes[k] = wn[k]; for (int a = 0; a < 3; ++a) pos[k][a] = wp[k][a]; }
+    if (sa_out) *sa_out = sa;
+    if (sb_out) *sb_out = sb;
+    free(wn);
+    free(wp);
+    return len;
+}
+
+int orc_film_geometry(const orc_sim* s, int nucleus_a, int nucleus_b, double* h, double* r_disc,
+                      int* n_lines)
+{
+    if (nucleus_a < 0 || nucleus_b < 0 || nucleus_a >= s->n_nuc || nucleus_b >= s->n_nuc)
+        return -1;
+    uint32_t la = s->comp[nucleus_a], lb = s->comp[nucleus_b];
+    if (la == 0 || lb == 0 || la == lb) return -4;
+    int ba = s->bub_of_label[la], bb = s->bub_of_label[lb];
+    const orc_bubble* A = &s->bub[ba];
+    const orc_bubble* B = &s->bub[bb];
+    int d = s->L.d;
+    double dv[3];
+    dv[0] = min_image(B->centroid[0] - A->centroid[0], s->nx);
+    dv[1] = min_image(B->centroid[1] - A->centroid[1], s->ny);
+    dv[2] = (d == 3) ? min_image(B->centroid[2] - A->centroid[2], s->nz) : 0.0;
+    double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    int T = (int)ceil(dist);
+    if (T <= 0) return -4;
+    /* unit axis and an orthonormal basis of the perpendicular plane (2D: one vector) */
+    double u[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist}, n1[3], n2[3] = {0.0, 0.0, 0.0};
+    if (d == 2) {
+        n1[0] = -u[1]; n1[1] = u[0]; n1[2] = 0.0;
+    } else {
+        /* n1 = u x z if that is not too short, else u x x */
+        double c[3] = {u[1], -u[0], 0.0};
+        if (c[0] * c[0] + c[1] * c[1] < 0.25) { c[0] = 0.0; c[1] = u[2]; c[2] = -u[1]; }
+        double cl = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        for (int a = 0; a < 3; ++a) n1[a] = c[a] / cl;
+        n2[0] = u[1] * n1[2] - u[2] * n1[1];
+        n2[1] = u[2] * n1[0] - u[0] * n1[2];
+        n2[2] = u[0] * n1[1] - u[1] * n1[0];
+    }
+    int K = (int)floor(A->radius < B->radius ? A->radius : B->radius);
+    int count = 0;
+    for (int i = -K; i <= K; ++i) {
+        for (int j = (d == 3 ? -K : 0); j <= (d == 3 ? K : 0); ++j) {
+            if (i * i + j * j > K * K) continue;
+            double off[3];
+            for (int a = 0; a < 3; ++a) off[a] = (double)i * n1[a] + (double)j * n2[a];
+            if (film_line(s, A->centroid, off, dv, T, la, lb, NULL, NULL, NULL, NULL) > 0) ++count;
+        }
+    }
+    *n_lines = count;
+    *r_disc = (d == 2) ? 0.5 * (double)count : sqrt((double)count / M_PI);
+    /* thickness on the centre line: distance between the rho = theta crossings, linear in the
+     * walk's arc length between the node centres on either side of each interface */
+    *h = -1.0;
+    int64_t* nodes = (int64_t*)malloc(sizeof(int64_t) * (size_t)(T + 1));
+    double(*pos)[3] = (double(*)[3])malloc(sizeof(double) * 3 * (size_t)(T + 1));
+    double zero[3] = {0.0, 0.0, 0.0};
+    int sa, sb;
+    if (film_line(s, A->centroid, zero, dv, T, la, lb, nodes, pos, &sa, &sb) > 0) {
+        double arc = 0.0, sA = 0.0, sB = 0.0;
+        for (int k = 1; k <= sb; ++k) {
+            double dx = pos[k][0] - pos[k - 1][0], dy = pos[k][1] - pos[k - 1][1],
+                   dz = pos[k][2] - pos[k - 1][2];
+            double seg = sqrt(dx * dx + dy * dy + dz * dz);
+            double r0 = node_density(s, s->f, nodes[k - 1]), r1 = node_density(s, s->f, nodes[k]);
+            if (k == sa + 1) sA = arc + seg * (s->theta - r0) / (r1 - r0);
+            if (k == sb) sB = arc + seg * (r0 - s->theta) / (r0 - r1);
+            arc += seg;
+        }
+        *h = sB - sA;
+    }
+    free(nodes);
+    free(pos);
+    return 0;
+}
+
 int orc_step(orc_sim* s, int nsteps)
 {
     for (int n = 0; n < nsteps; ++n) {

@@ -119,6 +119,17 @@ void orc_set_equilibrium(orc_sim* s, const double* rho, const double* u);
 /* Run a test pass now (as at seeding); returns 0 or -5. */
 int orc_test_pass(orc_sim* s);
 
+/* Film geometry of the pair of bubbles holding nuclei a and b at the last test pass (Sec. 3:
+ * the film as a disc of radius R_d and thickness h; Fig. 3).  Lines parallel to the centroid
+ * segment, shifted by integer multiples of an orthonormal basis of the perpendicular plane up to
+ * the smaller bubble radius, are walked like the merge test's centre line; *n_lines counts those
+ * that cross a film of 1..film_max liquid nodes between the two bubbles, *r_disc = n_lines/2
+ * (2D) or sqrt(n_lines/pi) (3D).  *h = distance between the rho = theta crossings on the centre
+ * line (linear in arc length), -1 if that line crosses no film.  Returns 0, -1 (bad nucleus)
+ * or -4 (the nuclei are not in two distinct bubbles). */
+int orc_film_geometry(const orc_sim* s, int nucleus_a, int nucleus_b, double* h, double* r_disc,
+                      int* n_lines);
+
 int64_t orc_time(const orc_sim* s);
 int64_t orc_num_nodes(const orc_sim* s);
 int orc_labels(const orc_sim* s, uint32_t* labels);                  /* last test pass */

@@ -194,6 +194,19 @@ int sc_nuclei(struct sc_sim* sim, uint32_t* comp, double* remaining);
  * bubble, else 1 + the smallest nucleus index of the criterion-merged group that owns the node.
  * All zero when the barrier is off.  Errors: SC_E_INVAL (NULL), SC_E_STATE, SC_E_DEVICE. */
 int sc_owner(struct sc_sim* sim, uint16_t* owner);
+/* Film geometry of the bubbles holding nuclei a and b at the last test pass (Sec. 3: the film
+ * as a disc of radius R_d and thickness h between two interfaces; Fig. 3: h_c and R_d at
+ * rupture).  Lines parallel to the centroid segment, shifted by integer multiples of an
+ * orthonormal basis of the perpendicular plane up to the smaller bubble radius (2D: one basis
+ * vector, the segment's normal; 3D: u x z, or u x x when u is nearly along z, and u x n1), are
+ * walked like the merge test's centre line.  *n_lines = the lines crossing a film of
+ * 1..film_max liquid nodes free of other labels; *r_disc = n_lines / 2 (2D) or
+ * sqrt(n_lines / pi) (3D); *h = distance between the rho = theta crossings on the centre line,
+ * linear in arc length between node centres, -1 if the centre line crosses no film.
+ * Errors: SC_E_INVAL (bad index, NULL), SC_E_STATE (no pass yet; nuclei not in two distinct
+ * bubbles), SC_E_DEVICE. */
+int sc_film_geometry(struct sc_sim* sim, int32_t nucleus_a, int32_t nucleus_b, double* h,
+                     double* r_disc, int32_t* n_lines);
 /* *rho0: the buoyancy reference density in use (0 when gravity is off).  Errors: SC_E_INVAL. */
 int sc_buoyancy_density(struct sc_sim* sim, double* rho0);
 int sc_time(struct sc_sim* sim, int64_t* step);

@@ -1090,6 +1090,75 @@ int sc_last_labels(sc_sim* s, uint32_t* labels)
     return SC_OK;
 }
 
+int sc_film_geometry(sc_sim* s, int32_t nucleus_a, int32_t nucleus_b, double* h,
+                     double* r_disc, int32_t* n_lines)
+{
+#pragma clang fp contract(off)
+    TRY(check_usable(s));
+    if (!h || !r_disc || !n_lines) return fail(SC_E_INVAL, "NULL output");
+    const int n = (int)s->rad.size();
+    if (nucleus_a < 0 || nucleus_b < 0 || nucleus_a >= n || nucleus_b >= n)
+        return fail(SC_E_INVAL, "nucleus index out of range");
+    if (!s->have_labels) return fail(SC_E_STATE, "no test pass has run");
+    const uint32_t la = s->comp[nucleus_a], lb = s->comp[nucleus_b];
+    if (la == 0 || lb == 0 || la == lb)
+        return fail(SC_E_STATE, "the nuclei are not in two distinct bubbles");
+    const sc_bubble* A = nullptr;
+    const sc_bubble* B = nullptr;
+    for (const sc_bubble& b : s->bub) {
+        if (b.label == la) A = &b;
+        if (b.label == lb) B = &b;
+    }
+    if (!A || !B) return fail(SC_E_STATE, "bubble not found");
+    FilmArgs g;
+    double dv[3];
+    dv[0] = min_image(B->centroid[0] - A->centroid[0], s->p.nx);
+    dv[1] = min_image(B->centroid[1] - A->centroid[1], s->p.ny);
+    dv[2] = (s->d == 3) ? min_image(B->centroid[2] - A->centroid[2], s->p.nz) : 0.0;
+    const double dist = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const int T = (int)std::ceil(dist);
+    if (T <= 0) return fail(SC_E_STATE, "coincident centroids");
+    // unit axis and an orthonormal basis of the perpendicular plane (2D: one vector)
+    const double u[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
+    double n1[3], n2[3] = {0.0, 0.0, 0.0};
+    if (s->d == 2) {
+        n1[0] = -u[1]; n1[1] = u[0]; n1[2] = 0.0;
+    } else {
+        double c[3] = {u[1], -u[0], 0.0};  // u x z, or u x x when that is short
+        if (c[0] * c[0] + c[1] * c[1] < 0.25) { c[0] = 0.0; c[1] = u[2]; c[2] = -u[1]; }
+        const double cl = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        for (int k = 0; k < 3; ++k) n1[k] = c[k] / cl;
+        n2[0] = u[1] * n1[2] - u[2] * n1[1];
+        n2[1] = u[2] * n1[0] - u[0] * n1[2];
+        n2[2] = u[0] * n1[1] - u[1] * n1[0];
+    }
+    for (int k = 0; k < 3; ++k) {
+        g.cen[k] = A->centroid[k];
+        g.dv[k] = dv[k];
+        g.n1[k] = n1[k];
+        g.n2[k] = n2[k];
+    }
+    g.label_a = la;
+    g.label_b = lb;
+    g.T = T;
+    g.K = (int)std::floor(std::min(A->radius, B->radius));
+    g.dim = s->d;
+    g.film_max = s->p.film_max;
+    TRY(ensure(s, s->small, 4096));
+    FilmOut* out_d = (FilmOut*)((char*)s->small.p + 256);
+    FilmOut init{0u, 0, -1.0};
+    HIPX(hipMemcpyAsync(out_d, &init, sizeof(init), hipMemcpyHostToDevice, s->stream));
+    HIPX(launch_film(s->q, s->p.storage, s->f[s->cur], (const uint32_t*)s->labels.p, g, out_d,
+                     field_args(s), s->stream));
+    FilmOut res;
+    HIPX(hipMemcpyAsync(&res, out_d, sizeof(res), hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    *n_lines = (int32_t)res.count;
+    *h = res.h;
+    *r_disc = s->d == 2 ? 0.5 * (double)res.count : std::sqrt((double)res.count / M_PI);
+    return SC_OK;
+}
+
 int sc_buoyancy_density(sc_sim* s, double* rho0)
 {
     TRY(check_usable(s));

@@ -132,6 +132,21 @@ hipError_t launch_merge(int q, int storage, const void* f, const uint32_t* label
                         const MergePair* pairs_d, MergeResult* res_d, int npairs, int film_max,
                         const FieldArgs& a, hipStream_t st);
 
+// Film geometry of a bubble pair (h and the line count behind R_d): lines parallel to the
+// centroid segment, at offsets i n1 + j n2 (i^2 + j^2 <= K^2), walked like the merge test.
+struct FilmArgs {
+    double cen[3], dv[3], n1[3], n2[3];
+    uint32_t label_a, label_b;
+    int32_t T, K, dim, film_max;
+};
+struct FilmOut {
+    unsigned int count;  // lines crossing a film of 1..film_max liquid nodes
+    int32_t pad;
+    double h;            // centre-line thickness (rho = theta crossings), -1 if no film there
+};
+hipError_t launch_film(int q, int storage, const void* f, const uint32_t* labels,
+                       const FilmArgs& g, FilmOut* out_d, const FieldArgs& a, hipStream_t st);
+
 // Blowing-agent source for one step: f_i(x) += w_i * add[slot] on the listed gas nodes.
 hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
                          const int32_t* list_slot, int64_t count, const double* add_d,

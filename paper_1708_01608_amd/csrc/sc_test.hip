@@ -2,6 +2,8 @@
 // merge criterion and blowing-agent source of libsc (gfx950).
 //
 // Every kernel reads the pull-layout populations: f_i(x, t) = stored_i(x - e_i) + w_i rho_ref.
+#include <algorithm>
+
 #include "sc_device.hpp"
 #include "sc_internal.hpp"
 
@@ -454,6 +456,91 @@ __global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_sl
     }
 }
 
+// ---- film geometry of a bubble pair (Sec. 3 film disc; Fig. 3) --------------------------------
+// Node of sample k on the line shifted by off, and its rounded (unwrapped) position r.
+template <int Q>
+__device__ __forceinline__ int64_t film_node(const FilmArgs& g, const double off[3], int k,
+                                             const FieldArgs& a, double r[3])
+{
+#pragma clang fp contract(off)
+    for (int c = 0; c < 3; ++c) {
+        const double q = g.cen[c] + off[c] + g.dv[c] * (double)k / (double)g.T;
+        r[c] = floor(q + 0.5);
+    }
+    if (lat<Q>::d == 2) r[2] = 0.0;
+    int x = (int)r[0] % a.nx; if (x < 0) x += a.nx;
+    int y = (int)r[1] % a.ny; if (y < 0) y += a.ny;
+    int z = 0;
+    if (lat<Q>::d == 3) { z = (int)r[2] % a.nz; if (z < 0) z += a.nz; }
+    return idx3(x, y, z, a.nx, a.ny);
+}
+
+// One thread per line (offset (i, j)); the centre line also measures h.  Three walks per line,
+// consecutive repeats dropped: the last node of bubble a, the first node of b after it, then the
+// run between (liquid only) and, on the centre line, the arc positions of the two crossings.
+template <int Q, typename S>
+__global__ void k_film(const S* f, const uint32_t* labels, FilmArgs g, FilmOut* out,
+                       FieldArgs a)
+{
+#pragma clang fp contract(off)
+    const int side = 2 * g.K + 1;
+    const int nlines = g.dim == 3 ? side * side : side;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nlines;
+         t += gridDim.x * blockDim.x) {
+        const int i = t % side - g.K;
+        const int j = g.dim == 3 ? t / side - g.K : 0;
+        if (i * i + j * j > g.K * g.K) continue;
+        double off[3], r[3];
+        for (int c = 0; c < 3; ++c) off[c] = (double)i * g.n1[c] + (double)j * g.n2[c];
+        int sa = -1, sb = -1, pos = -1;
+        int64_t prev = -1;
+        for (int k = 0; k <= g.T; ++k) {
+            const int64_t nd = film_node<Q>(g, off, k, a, r);
+            if (nd == prev) continue;
+            prev = nd;
+            ++pos;
+            if (labels[nd] == g.label_a) sa = pos;
+        }
+        if (sa < 0) continue;
+        prev = -1; pos = -1;
+        for (int k = 0; k <= g.T && sb < 0; ++k) {
+            const int64_t nd = film_node<Q>(g, off, k, a, r);
+            if (nd == prev) continue;
+            prev = nd;
+            ++pos;
+            if (pos > sa && labels[nd] == g.label_b) sb = pos;
+        }
+        const int len = sb >= 0 ? sb - sa - 1 : 0;
+        if (len < 1 || len > g.film_max) continue;
+        const bool centre = i == 0 && j == 0;
+        bool clean = true;
+        double arc = 0.0, sA = 0.0, sB = 0.0, rp[3] = {0.0, 0.0, 0.0}, rho_p = 0.0;
+        prev = -1; pos = -1;
+        for (int k = 0; k <= g.T && pos < sb; ++k) {
+            const int64_t nd = film_node<Q>(g, off, k, a, r);
+            if (nd == prev) continue;
+            prev = nd;
+            ++pos;
+            if (pos > sa && pos < sb && labels[nd] != 0) clean = false;
+            if (centre) {
+                const double rho = rho_d<Q, S>(f, nd, a);
+                if (pos >= 1) {
+                    const double dx = r[0] - rp[0], dy = r[1] - rp[1], dz = r[2] - rp[2];
+                    const double seg = sqrt(dx * dx + dy * dy + dz * dz);
+                    if (pos == sa + 1) sA = arc + seg * (a.theta - rho_p) / (rho - rho_p);
+                    if (pos == sb) sB = arc + seg * (rho_p - a.theta) / (rho_p - rho);
+                    arc += seg;
+                }
+                rho_p = rho;
+                for (int c = 0; c < 3; ++c) rp[c] = r[c];
+            }
+        }
+        if (!clean) continue;
+        atomicAdd(&out->count, 1u);
+        if (centre) out->h = sB - sA;
+    }
+}
+
 // ---- barrier owner field ---------------------------------------------------------------------
 // Seed: a gas node of a bubble (a component holding nuclei) gets that bubble's owner id.
 __global__ void k_owner_seed(const uint32_t* labels, const int32_t* slot_of_root,
@@ -694,6 +781,18 @@ hipError_t launch_owner_seed(const uint32_t* labels, const int32_t* slot_of_root
 {
     hipLaunchKernelGGL(k_owner_seed, grid_for(N), dim3(256), 0, st, labels, slot_of_root, ids_d,
                        nb, owner, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_film(int q, int storage, const void* f, const uint32_t* labels,
+                       const FilmArgs& g, FilmOut* out_d, const FieldArgs& a, hipStream_t st)
+{
+    const int side = 2 * g.K + 1;
+    const int nlines = g.dim == 3 ? side * side : side;
+    const dim3 grid((unsigned)std::max(1, std::min(1024, (nlines + 255) / 256)));
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_film<QQ, SS>), grid, dim3(256), 0, st, (const SS*)f,
+                                   labels, g, out_d, a));
     return hipGetLastError();
 }
 

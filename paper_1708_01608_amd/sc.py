@@ -96,7 +96,7 @@ class BatchResult(C.Structure):
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
     "sc_seed_nuclei", "sc_step", "sc_fields", "sc_laplacian_p", "sc_label_bubbles",
-    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_owner", "sc_buoyancy_density", "sc_time",
+    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_time",
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
@@ -139,6 +139,7 @@ def load_library(path=LIB_PATH):
         "sc_nuclei": (C.c_int, [P, P, P]),
         "sc_owner": (C.c_int, [P, P]),
         "sc_buoyancy_density": (C.c_int, [P, P]),
+        "sc_film_geometry": (C.c_int, [P, C.c_int32, C.c_int32, P, P, P]),
         "sc_time": (C.c_int, [P, P]),
         "sc_lattice": (C.c_int, [C.c_int32, P, P]),
         "sc_get_populations": (C.c_int, [P, P]),
@@ -336,6 +337,13 @@ class Sim:
         nc = C.c_int64()
         _check(self._lib.sc_label_bubbles(self._h, _ptr(m), _ptr(lab), C.byref(nc)))
         return lab, nc.value
+
+    def film_geometry(self, a, b):
+        """(h, R_d, n_lines) of the bubbles holding nuclei a and b at the last test pass."""
+        h, r, n = C.c_double(), C.c_double(), C.c_int32()
+        _check(self._lib.sc_film_geometry(self._h, int(a), int(b), C.byref(h), C.byref(r),
+                                          C.byref(n)))
+        return h.value, r.value, n.value
 
     @property
     def rho0(self):

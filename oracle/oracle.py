@@ -73,6 +73,11 @@ def _load():
     lib.orc_uniform.argtypes = [C.c_uint64, C.c_uint64]
     lib.orc_splitmix64.restype = C.c_uint64
     lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_set_two_component.restype = C.c_int
+    lib.orc_set_two_component.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double]
+    lib.orc_gas_density.argtypes = [P, P]
+    lib.orc_set_gas_equilibrium.restype = C.c_int
+    lib.orc_set_gas_equilibrium.argtypes = [P, P]
     lib.orc_film_geometry.restype = C.c_int
     lib.orc_film_geometry.argtypes = [P, C.c_int, C.c_int, P, P, P]
     lib.orc_set_gravity.restype = C.c_int
@@ -136,7 +141,7 @@ class OracleSim:
 
     def __init__(self, q, nx, ny, nz=1, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16, amp=1e-3,
                  seed=1, theta=0.0, K=10, film_max=8, barrier=False, corona=3, gravity=None,
-                 rho0=0.0):
+                 rho0=0.0, two_component=None):
         self._lib = _load()
         self.q, self.nx, self.ny, self.nz = q, nx, ny, nz
         self.d = 2 if q == 9 else 3
@@ -147,6 +152,9 @@ class OracleSim:
         if not h:
             raise ValueError("oracle rejected the parameters")
         self._h = C.c_void_p(h)
+        if two_component is not None:  # (Gx, tau_v, rho_vapour, rho_dissolved)
+            if self._lib.orc_set_two_component(self._h, *[float(v) for v in two_component]) != 0:
+                raise ValueError("bad two-component parameters")
         if barrier:
             self.set_barrier(True, corona)
         if gravity is not None:
@@ -172,6 +180,16 @@ class OracleSim:
     def set_barrier(self, on, corona=3):
         if self._lib.orc_set_barrier(self._h, 1 if on else 0, int(corona)) != 0:
             raise ValueError("corona must be >= 0")
+
+    def set_gas_equilibrium(self, rho_v):
+        r = np.ascontiguousarray(rho_v, dtype=np.float64).reshape(self.N)
+        if self._lib.orc_set_gas_equilibrium(self._h, _ptr(r)) != 0:
+            raise ValueError("no gas component")
+
+    def gas_density(self):
+        rv = np.zeros(self.N)
+        self._lib.orc_gas_density(self._h, _ptr(rv))
+        return rv
 
     def film_geometry(self, a, b):
         """(h, R_d, n_lines) of the bubbles holding nuclei a and b at the last test pass."""

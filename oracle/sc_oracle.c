@@ -140,6 +140,13 @@ struct orc_sim {
     double psi_l;      /* psi(rho_l): what a bubble sees where another bubble's lattice is */
     int32_t* owner;    /* [N] owner id of each node (0: nobody), rebuilt at every test pass */
 
+    /* two components (liquid, gas; off unless orc_set_two_component): Shan-Doolen mixture with
+     * psi = rho and a cross interaction Gx; fv/fvn are the gas component's populations */
+    int ncomp;
+    double Gx, tau_v, rho_vap, rho_dis;
+    double* fv;
+    double* fvn;
+
     /* gravity (drainage, Sec. 3; off unless orc_set_gravity): body force (rho - rho0) g */
     double g[3];
     double rho0;       /* buoyancy reference density */
@@ -278,7 +285,8 @@ orc_sim* orc_create(int q, int nx, int ny, int nz, double tau, double G, double 
 void orc_destroy(orc_sim* s)
 {
     if (!s) return;
-    free(s->f); free(s->fn); free(s->labels); free(s->owner); free(s->bub_of_label); free(s->bub);
+    free(s->f); free(s->fn); free(s->fv); free(s->fvn); free(s->labels); free(s->owner);
+    free(s->bub_of_label); free(s->bub);
     free(s->cen); free(s->rad); free(s->rem); free(s->nuc_node); free(s->comp);
     free(s->merge_parent); free(s->topo_parent); free(s->ev); free(s->tev);
     free(s);
@@ -370,6 +378,9 @@ int orc_seed_nuclei(orc_sim* s, int n, const double* centre, const double* radiu
         if (gas) {
             double rho = s->rho_g + s->amp * (2.0 * orc_uniform(s->seed, (uint64_t)x) - 1.0);
             for (int i = 0; i < q; ++i) s->f[(int64_t)i * N + x] = feq_one(&s->L, i, rho, zero);
+            if (s->ncomp == 2)  /* the bubble is filled with the gas component */
+                for (int i = 0; i < q; ++i)
+                    s->fv[(int64_t)i * N + x] = feq_one(&s->L, i, s->rho_vap, zero);
         }
     }
     /* the buoyancy reference follows the seeded box when it is the mean density */
@@ -382,8 +393,64 @@ int orc_seed_nuclei(orc_sim* s, int n, const double* centre, const double* radiu
 /* ------------------------------------------------------------------------------------------ */
 /* One time step: moments, pseudopotential, force, forced BGK collision, streaming.            */
 /* ------------------------------------------------------------------------------------------ */
+/* Cross interaction of the two-component mixture (Shan & Doolen): the force on component a at x
+ * is -Gx rho_a(x) sum_{i != 0} w_i rho_b(x + e_i) e_i, b the other component (psi = rho). */
+static void cross_force(const orc_sim* s, const double* rho_a, const double* rho_b, int64_t x,
+                        double F[3])
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < s->L.q; ++i) {
+        if (s->L.e[i][0] == 0 && s->L.e[i][1] == 0 && s->L.e[i][2] == 0) continue;
+        double rn = rho_b[neighbour(s, x, i)];
+        for (int a = 0; a < 3; ++a) acc[a] += s->L.w[i] * rn * s->L.e[i][a];
+    }
+    for (int a = 0; a < 3; ++a) F[a] = -s->Gx * rho_a[x] * acc[a];
+}
+
+/* Two-component step: common velocity u' = sum_a (j_a / tau_a) / sum_a (rho_a / tau_a); each
+ * component relaxes to its equilibrium at u' + tau_a F_a / rho_a with its own tau, then streams. */
+static void collide_stream_2c(orc_sim* s)
+{
+    int64_t N = s->N;
+    int q = s->L.q;
+    double* rl = (double*)malloc(sizeof(double) * (size_t)N);
+    double* rv = (double*)malloc(sizeof(double) * (size_t)N);
+    for (int64_t x = 0; x < N; ++x) {
+        rl[x] = node_density(s, s->f, x);
+        rv[x] = node_density(s, s->fv, x);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        double jl[3], jv[3], Fl[3], Fv[3], up[3], ul[3], uv[3];
+        node_momentum(s, s->f, x, jl);
+        node_momentum(s, s->fv, x, jv);
+        cross_force(s, rl, rv, x, Fl);
+        cross_force(s, rv, rl, x, Fv);
+        double den = rl[x] / s->tau + rv[x] / s->tau_v;
+        for (int a = 0; a < 3; ++a) {
+            up[a] = (jl[a] / s->tau + jv[a] / s->tau_v) / den;
+            ul[a] = up[a] + s->tau * Fl[a] / rl[x];
+            uv[a] = up[a] + s->tau_v * Fv[a] / rv[x];
+        }
+        for (int i = 0; i < q; ++i) {
+            double fl = s->f[(int64_t)i * N + x], fv = s->fv[(int64_t)i * N + x];
+            int64_t y = neighbour(s, x, i);
+            s->fn[(int64_t)i * N + y] = fl - (fl - feq_one(&s->L, i, rl[x], ul)) / s->tau;
+            s->fvn[(int64_t)i * N + y] = fv - (fv - feq_one(&s->L, i, rv[x], uv)) / s->tau_v;
+        }
+    }
+    double* tmp = s->f; s->f = s->fn; s->fn = tmp;
+    tmp = s->fv; s->fv = s->fvn; s->fvn = tmp;
+    free(rl);
+    free(rv);
+}
+
 static void collide_stream(orc_sim* s)
 {
+    if (s->ncomp == 2) {
+        collide_stream_2c(s);
+        return;
+    }
     int64_t N = s->N;
     int q = s->L.q;
     double* psi = (double*)malloc(sizeof(double) * (size_t)N);
@@ -440,9 +507,63 @@ static void growth_source(orc_sim* s)
         if (lab == 0) continue;
         int b = s->bub_of_label[lab];
         if (b < 0 || add[b] == 0.0) continue;
-        for (int i = 0; i < q; ++i) s->f[(int64_t)i * N + x] += s->L.w[i] * add[b];
+        /* the agent's gas goes to the gas component when there is one */
+        double* target = s->ncomp == 2 ? s->fv : s->f;
+        for (int i = 0; i < q; ++i) target[(int64_t)i * N + x] += s->L.w[i] * add[b];
     }
     free(add);
+}
+
+/* EOS of the two-component mixture: p = (rho_l + rho_v)/3 + (Gx/3) rho_l rho_v (the bulk
+ * pressure of the cross interaction with psi = rho and cs^2 = 1/3). */
+static double pressure_2c(double rl, double rv, double Gx)
+{
+    return (rl + rv) / 3.0 + (Gx / 3.0) * rl * rv;
+}
+
+/* EOS pressure of node x: one- or two-component. */
+static double node_pressure(const orc_sim* s, int64_t x)
+{
+    if (s->ncomp == 2)
+        return pressure_2c(node_density(s, s->f, x), node_density(s, s->fv, x), s->Gx);
+    return pressure_of(node_density(s, s->f, x), s->G);
+}
+
+int orc_set_two_component(orc_sim* s, double Gx, double tau_v, double rho_vapour,
+                          double rho_dissolved)
+{
+    if (!isfinite(Gx) || !(tau_v > 0.5) || !(rho_vapour > 0.0) || !(rho_dissolved > 0.0))
+        return -1;
+    int64_t N = s->N;
+    int q = s->L.q;
+    s->fv = (double*)malloc(sizeof(double) * (size_t)q * (size_t)N);
+    s->fvn = (double*)malloc(sizeof(double) * (size_t)q * (size_t)N);
+    if (!s->fv || !s->fvn) return -2;
+    s->ncomp = 2;
+    s->Gx = Gx;
+    s->tau_v = tau_v;
+    s->rho_vap = rho_vapour;
+    s->rho_dis = rho_dissolved;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    /* the liquid holds rho_dissolved of the gas component everywhere until nuclei are painted */
+    for (int64_t x = 0; x < N; ++x)
+        for (int i = 0; i < q; ++i) s->fv[(int64_t)i * N + x] = feq_one(&s->L, i, rho_dissolved, zero);
+    return 0;
+}
+
+int orc_set_gas_equilibrium(orc_sim* s, const double* rho_v)
+{
+    if (s->ncomp != 2) return -1;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    for (int64_t x = 0; x < s->N; ++x)
+        for (int i = 0; i < s->L.q; ++i)
+            s->fv[(int64_t)i * s->N + x] = feq_one(&s->L, i, rho_v[x], zero);
+    return 0;
+}
+
+void orc_gas_density(const orc_sim* s, double* rho_v)
+{
+    for (int64_t x = 0; x < s->N; ++x) rho_v[x] = s->ncomp == 2 ? node_density(s, s->fv, x) : 0.0;
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -603,6 +724,11 @@ static int test_pass(orc_sim* s, int with_criterion)
             node_momentum(s, s->f, x, j);
             M += rho[x];
             for (int a = 0; a < 3; ++a) J[a] += j[a];
+            if (s->ncomp == 2) {
+                node_momentum(s, s->fv, x, j);
+                M += node_density(s, s->fv, x);
+                for (int a = 0; a < 3; ++a) J[a] += j[a];
+            }
         }
         if (!isfinite(M) || !isfinite(J[0]) || !isfinite(J[1]) || !isfinite(J[2]))
             s->numeric_error = 1;
@@ -739,10 +865,10 @@ static int test_pass(orc_sim* s, int with_criterion)
                 for (int k = sa + 2; k < sb; ++k)
                     if (rho[walk[k]] > rho[cstar]) cstar = walk[k];
                 /* lattice Laplacian of the EOS pressure at c* */
-                double pc = pressure_of(rho[cstar], s->G), lap = 0.0;
+                double pc = node_pressure(s, cstar), lap = 0.0;
                 for (int i = 0; i < s->L.q; ++i) {
                     if (s->L.e[i][0] == 0 && s->L.e[i][1] == 0 && s->L.e[i][2] == 0) continue;
-                    lap += s->L.w[i] * (pressure_of(rho[neighbour(s, cstar, i)], s->G) - pc);
+                    lap += s->L.w[i] * (node_pressure(s, neighbour(s, cstar, i)) - pc);
                 }
                 lap *= 6.0;
                 if (lap >= 0.0) {
@@ -920,13 +1046,41 @@ int orc_step(orc_sim* s, int nsteps)
 /* ------------------------------------------------------------------------------------------ */
 /* Output fields                                                                               */
 /* ------------------------------------------------------------------------------------------ */
+static void fields_2c(const orc_sim* s, double* rho, double* u)
+{
+    int64_t N = s->N;
+    int d = s->L.d;
+    double* rl = (double*)malloc(sizeof(double) * (size_t)N);
+    double* rv = (double*)malloc(sizeof(double) * (size_t)N);
+    for (int64_t x = 0; x < N; ++x) {
+        rl[x] = node_density(s, s->f, x);
+        rv[x] = node_density(s, s->fv, x);
+    }
+    for (int64_t x = 0; x < N; ++x) {
+        if (rho) rho[x] = rl[x];
+        if (!u) continue;
+        /* barycentric velocity of the mixture: (j_l + j_v + (F_l + F_v)/2) / (rho_l + rho_v) */
+        double jl[3], jv[3], Fl[3], Fv[3];
+        node_momentum(s, s->f, x, jl);
+        node_momentum(s, s->fv, x, jv);
+        cross_force(s, rl, rv, x, Fl);
+        cross_force(s, rv, rl, x, Fv);
+        for (int a = 0; a < d; ++a)
+            u[(int64_t)a * N + x] = (jl[a] + jv[a] + 0.5 * (Fl[a] + Fv[a])) / (rl[x] + rv[x]);
+    }
+    free(rl);
+    free(rv);
+}
+
 void orc_fields(const orc_sim* s, double* rho, double* u, double* totals)
 {
     int64_t N = s->N;
     int d = s->L.d;
     double* psi = (double*)malloc(sizeof(double) * (size_t)N);
     psi_field(s, psi);
-    if (rho || u) {
+    if ((rho || u) && s->ncomp == 2) {
+        fields_2c(s, rho, u);
+    } else if (rho || u) {
 #pragma omp parallel for schedule(static)
         for (int64_t x = 0; x < N; ++x) {
             double r = node_density(s, s->f, x);
@@ -948,6 +1102,11 @@ void orc_fields(const orc_sim* s, double* rho, double* u, double* totals)
             node_momentum(s, s->f, x, j);
             M += node_density(s, s->f, x);
             for (int a = 0; a < 3; ++a) J[a] += j[a];
+            if (s->ncomp == 2) {  /* totals of the mixture */
+                node_momentum(s, s->fv, x, j);
+                M += node_density(s, s->fv, x);
+                for (int a = 0; a < 3; ++a) J[a] += j[a];
+            }
         }
         totals[0] = M; totals[1] = J[0]; totals[2] = J[1]; totals[3] = J[2];
     }
@@ -958,6 +1117,23 @@ void orc_force(const orc_sim* s, double* F)
 {
     int64_t N = s->N;
     int d = s->L.d;
+    if (s->ncomp == 2) {  /* the mixture's total interaction force F_l + F_v */
+        double* rl = (double*)malloc(sizeof(double) * (size_t)N);
+        double* rv = (double*)malloc(sizeof(double) * (size_t)N);
+        for (int64_t x = 0; x < N; ++x) {
+            rl[x] = node_density(s, s->f, x);
+            rv[x] = node_density(s, s->fv, x);
+        }
+        for (int64_t x = 0; x < N; ++x) {
+            double Fl[3], Fv[3];
+            cross_force(s, rl, rv, x, Fl);
+            cross_force(s, rv, rl, x, Fv);
+            for (int a = 0; a < d; ++a) F[(int64_t)a * N + x] = Fl[a] + Fv[a];
+        }
+        free(rl);
+        free(rv);
+        return;
+    }
     double* psi = (double*)malloc(sizeof(double) * (size_t)N);
     psi_field(s, psi);
 #pragma omp parallel for schedule(static)
@@ -974,7 +1150,7 @@ void orc_laplacian_p(const orc_sim* s, double* p, double* lap)
     int64_t N = s->N;
     double* pp = (double*)malloc(sizeof(double) * (size_t)N);
 #pragma omp parallel for schedule(static)
-    for (int64_t x = 0; x < N; ++x) pp[x] = pressure_of(node_density(s, s->f, x), s->G);
+    for (int64_t x = 0; x < N; ++x) pp[x] = node_pressure(s, x);
     if (p) memcpy(p, pp, sizeof(double) * (size_t)N);
     if (lap) {
 #pragma omp parallel for schedule(static)

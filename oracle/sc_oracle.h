@@ -88,6 +88,23 @@ int orc_set_barrier(orc_sim* s, int on, int corona);
 /* owner[N]: 0 = nobody, else 1 + the smallest nucleus index of the owning merged group. */
 int orc_owner(const orc_sim* s, int32_t* owner);
 
+/* Two components (a liquid and a gas, so that the blowing agent's gas grows the bubbles):
+ * Shan-Doolen mixture with psi = rho, the force on component a being
+ * -Gx rho_a(x) sum_i w_i rho_b(x + e_i) e_i, a common velocity
+ * u' = sum_a (j_a / tau_a) / sum_a (rho_a / tau_a), equilibria at u' + tau_a F_a / rho_a.  The
+ * liquid component keeps the existing populations (rho_l, rho_g, theta and labels refer to it;
+ * G is not used); the gas component fills the box with rho_dissolved and painted nuclei with
+ * rho_vapour; the blowing agent feeds the gas component; the criterion uses
+ * p = (rho_l + rho_v)/3 + (Gx/3) rho_l rho_v; fields report the liquid density and the mixture's
+ * barycentric velocity (j_l + j_v + (F_l + F_v)/2) / (rho_l + rho_v); totals sum both components.
+ * Call before seeding.  Returns 0, -1 (bad parameters) or -2 (no memory). */
+int orc_set_two_component(orc_sim* s, double Gx, double tau_v, double rho_vapour,
+                          double rho_dissolved);
+/* Gas component at rest with density rho_v[N] (two-component mode only; else returns -1). */
+int orc_set_gas_equilibrium(orc_sim* s, const double* rho_v);
+/* rho_v[N]: density of the gas component (zeros with one component). */
+void orc_gas_density(const orc_sim* s, double* rho_v);
+
 /* Gravity (drainage; the paper's runs leave it out): a body force (rho - rho0) g is added to the
  * Shan-Chen force of every node, in the collision and in the reported velocity.  g is [3] (z
  * ignored in 2D).  rho0 <= 0 selects the mean density of the box, taken now and again when
@@ -104,7 +121,8 @@ int orc_step(orc_sim* s, int nsteps);
 void orc_fields(const orc_sim* s, double* rho, double* u, double* totals);
 /* p[N] = rho/3 + (G/6) psi^2 and lap[N] = 6 sum_i w_i (p(x+e_i) - p(x)); NULL skips. */
 void orc_laplacian_p(const orc_sim* s, double* p, double* lap);
-/* F[d][N], the Shan-Chen force on the current state (with the barrier when it is on). */
+/* F[d][N], the Shan-Chen force on the current state (with the barrier when it is on; the
+ * mixture's total F_l + F_v in two-component mode). */
 void orc_force(const orc_sim* s, double* F);
 
 /* Canonical periodic labelling of a mask: label = 1 + smallest linear index of the component,

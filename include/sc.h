@@ -102,6 +102,23 @@ typedef struct sc_params {
      * only (SC_E_UNSUPPORTED otherwise, and with step_variant 2); gravity[2] is ignored in 2D. */
     double gravity[3];         /* g in lattice units; all zero (default) = off */
     double rho_buoyancy;       /* rho0; <= 0 selects the mean density */
+    /* Two components (Sec. 3: the agent's gas raises bubble volume; Sec. 3.1: two simulations
+     * run together for the two-phase model): a liquid and a gas component (Shan-Doolen mixture,
+     * psi = rho; force on component a: -G_cross rho_a(x) sum_i w_i rho_b(x + e_i) e_i; common
+     * velocity u' = sum_a (j_a/tau_a) / sum_a (rho_a/tau_a); equilibria at u' + tau_a F_a/rho_a).
+     * rho_liquid / rho_gas / gas_threshold, labels, bubbles and the film walk refer to the liquid
+     * component (G is not used); the gas component fills the box with rho_dissolved and painted
+     * nuclei with rho_vapour; the blowing agent feeds the gas component; the criterion's EOS is
+     * p = (rho_l + rho_v)/3 + (G_cross/3) rho_l rho_v; totals sum both components; sc_fields
+     * reports the liquid density and the mixture's barycentric velocity
+     * (j_l + j_v + (F_l + F_v)/2) / (rho_l + rho_v); population access concerns the liquid.
+     * FP32 storage and FP64 arithmetic only, no barrier, no gravity (SC_E_UNSUPPORTED). */
+    int32_t components;        /* 1 (default) or 2 */
+    int32_t reserved2;
+    double G_cross;            /* cross interaction, > 0 repels (default 1.5) */
+    double tau_vapour;         /* BGK time of the gas component; <= 0 selects tau */
+    double rho_vapour;         /* gas component in painted nuclei (default 1.0) */
+    double rho_dissolved;      /* gas component elsewhere at creation (default 0.05) */
 } sc_params;
 
 /* One firing of the merge criterion (Sec. 3.1 eta_m: 1 -> 0; Sec. 4 film rupture). */
@@ -207,6 +224,11 @@ int sc_owner(struct sc_sim* sim, uint16_t* owner);
  * bubbles), SC_E_DEVICE. */
 int sc_film_geometry(struct sc_sim* sim, int32_t nucleus_a, int32_t nucleus_b, double* h,
                      double* r_disc, int32_t* n_lines);
+/* rho_v[N] (host): density of the gas component (FP64 arithmetic, FP32 out); zeros with one
+ * component.  Errors: SC_E_INVAL (NULL), SC_E_STATE, SC_E_DEVICE. */
+int sc_gas_density(struct sc_sim* sim, float* rho_v);
+/* Gas component at rest with density rho_v[N] (> 0); two components only (SC_E_STATE). */
+int sc_set_gas_equilibrium(struct sc_sim* sim, const double* rho_v);
 /* *rho0: the buoyancy reference density in use (0 when gravity is off).  Errors: SC_E_INVAL. */
 int sc_buoyancy_density(struct sc_sim* sim, double* rho0);
 int sc_time(struct sc_sim* sim, int64_t* step);

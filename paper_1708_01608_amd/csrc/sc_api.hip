@@ -73,6 +73,13 @@ struct sc_sim {
     bool grav = false;
     double rho0 = 0.0;
 
+    // two-component mode: the gas component's populations (same layout and cur as f) and the
+    // FP64 densities of both components that its step reads
+    bool two = false;
+    void* fv[2] = {nullptr, nullptr};
+    DevBuf dens2;
+    double tau_v = 1.0;
+
     // nuclei (Sec. 3.1) and agent budgets (Sec. 3)
     std::vector<double> cen, rad, rem;
     double rate = 0.0;
@@ -181,6 +188,19 @@ FieldArgs field_args(const sc_sim* s)
     a.grav = s->grav ? 1 : 0;
     for (int c = 0; c < 3; ++c) a.gd[c] = s->p.gravity[c];
     a.rho0d = s->rho0;
+    a.f2 = s->two ? s->fv[s->cur] : nullptr;
+    a.Gx = s->p.G_cross;
+    return a;
+}
+
+Step2cArgs step2c_args(const sc_sim* s)
+{
+    Step2cArgs a;
+    a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
+    a.N = s->N;
+    a.tau_l = s->p.tau;
+    a.tau_v = s->tau_v;
+    a.Gx = s->p.G_cross;
     return a;
 }
 
@@ -412,6 +432,14 @@ int totals_now(sc_sim* s, double out[4])
                        s->stream));
     HIPX(hipMemcpyAsync(out, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPX(hipStreamSynchronize(s->stream));
+    if (s->two) {  // the mixture's totals: both components
+        double gas[4];
+        HIPX(launch_totals(s->q, s->p.storage, s->fv[s->cur], (double*)s->partials.p, out_d, fa,
+                           s->stream));
+        HIPX(hipMemcpyAsync(gas, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPX(hipStreamSynchronize(s->stream));
+        for (int c = 0; c < 4; ++c) out[c] += gas[c];
+    }
     return SC_OK;
 }
 
@@ -748,6 +776,20 @@ int validate(const sc_params* p)
         return fail(SC_E_INVAL, "corona must be in [0, 64]");
     if (p->barrier && p->storage != SC_STORE_F32)
         return fail(SC_E_UNSUPPORTED, "the barrier is offered on FP32 storage only");
+    if (p->components != 1 && p->components != 2) return fail(SC_E_INVAL, "components must be 1 or 2");
+    if (p->components == 2) {
+        if (!std::isfinite(p->G_cross)) return fail(SC_E_INVAL, "G_cross must be finite");
+        if (!(p->rho_vapour > 0.0) || !(p->rho_dissolved > 0.0) || !std::isfinite(p->rho_vapour) ||
+            !std::isfinite(p->rho_dissolved))
+            return fail(SC_E_INVAL, "rho_vapour and rho_dissolved must be > 0");
+        if (p->tau_vapour > 0.0 && !(p->tau_vapour > 0.5))
+            return fail(SC_E_INVAL, "tau_vapour must be > 0.5 (or <= 0 for tau)");
+        if (p->storage != SC_STORE_F32 || p->compute == SC_COMPUTE_F32)
+            return fail(SC_E_UNSUPPORTED, "two components run on FP32 storage, FP64 arithmetic");
+        if (p->barrier) return fail(SC_E_UNSUPPORTED, "no barrier with two components");
+        if (p->gravity[0] != 0.0 || p->gravity[1] != 0.0 || p->gravity[2] != 0.0)
+            return fail(SC_E_UNSUPPORTED, "no gravity with two components");
+    }
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(p->gravity[c])) return fail(SC_E_INVAL, "gravity must be finite");
     if (!std::isfinite(p->rho_buoyancy)) return fail(SC_E_INVAL, "rho_buoyancy must be finite");
@@ -779,6 +821,9 @@ void release(sc_sim* s)
         dev_free(s, b->p);
     dev_free(s, s->f[0]);
     dev_free(s, s->f[1]);
+    dev_free(s, s->fv[0]);
+    dev_free(s, s->fv[1]);
+    dev_free(s, s->dens2.p);
     for (auto& r : s->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -815,6 +860,11 @@ int sc_params_init(sc_params* p)
     p->rho_ref = -1.0;
     p->barrier = 0;
     p->corona = 3;
+    p->components = 1;
+    p->G_cross = 1.5;
+    p->tau_vapour = 0.0;
+    p->rho_vapour = 1.0;
+    p->rho_dissolved = 0.05;
     return SC_OK;
 }
 
@@ -875,7 +925,23 @@ int sc_create(const sc_params* p, sc_sim** out)
             return fail(SC_E_NOMEM, "owner field");
         }
     }
+    s->two = p->components == 2;
+    if (s->two) {
+        s->tau_v = p->tau_vapour > 0.0 ? p->tau_vapour : p->tau;
+        s->fv[0] = dev_alloc(s, bytes);
+        s->fv[1] = dev_alloc(s, bytes);
+        if (!s->fv[0] || !s->fv[1] || ensure(s, s->dens2, sizeof(double) * 2 * (size_t)s->N) != SC_OK) {
+            release(s);
+            delete s;
+            return fail(SC_E_NOMEM, "gas component buffers");
+        }
+    }
     hipError_t e = launch_init(s->q, p->storage, s->f[0], init_args(s, p->rho_liquid), s->stream);
+    if (e == hipSuccess && s->two) {  // the liquid holds rho_dissolved of the gas component
+        InitArgs ga = init_args(s, p->rho_dissolved);
+        ga.amp = 0.0;
+        e = launch_init(s->q, p->storage, s->fv[0], ga, s->stream);
+    }
     if (e == hipSuccess && p->barrier)
         e = launch_owner_seed(nullptr, nullptr, nullptr, 0, (uint16_t*)s->owner.p, s->N, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -936,10 +1002,15 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
         s->topo_parent[k] = k;
     }
     const InitArgs ia = init_args(s, s->p.rho_gas);
+    InitArgs va = init_args(s, s->p.rho_vapour);  // the bubbles are filled with the gas component
+    va.amp = 0.0;
     for (int k = 0; k < n; ++k) {
         if (s->rad[k] < 0.0) continue;
         HIPX(launch_paint(s->q, s->p.storage, s->f[s->cur], ia, &s->cen[3 * k], s->rad[k],
                           s->stream));
+        if (s->two)
+            HIPX(launch_paint(s->q, s->p.storage, s->fv[s->cur], va, &s->cen[3 * k], s->rad[k],
+                              s->stream));
     }
     if (s->grav) TRY(set_rho0(s));
     return test_pass(s, false);
@@ -955,8 +1026,13 @@ int sc_step(sc_sim* s, int32_t nsteps)
     for (int it = 0; it < nsteps; ++it) {
         hipEvent_t pe;
         TRY(prof_begin(s, SC_KERNEL_STEP, &pe));
-        HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a,
-                         s->shape, s->stream));
+        if (s->two)
+            HIPX(launch_step2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
+                               (float*)s->f[s->cur ^ 1], (float*)s->fv[s->cur ^ 1],
+                               (double*)s->dens2.p, step2c_args(s), s->stream));
+        else
+            HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a,
+                             s->shape, s->stream));
         if (s->p.barrier && s->frontier_count > 0)
             HIPX(launch_barrier_fix(s->q, s->p.storage, s->compute, s->f[s->cur],
                                     s->f[s->cur ^ 1], a, (const uint32_t*)s->frontier.p,
@@ -971,7 +1047,9 @@ int sc_step(sc_sim* s, int32_t nsteps)
         const int nb = (int)s->bub.size();
         if (s->step_active.size() && s->step_active[s->chunk_pos] && s->list_count > 0) {
             TRY(prof_begin(s, SC_KERNEL_SOURCE, &pe));
-            HIPX(launch_source(s->q, s->p.storage, s->f[s->cur], (const uint32_t*)s->list_node.p,
+            // the agent's gas goes to the gas component when there is one
+            HIPX(launch_source(s->q, s->p.storage, s->two ? s->fv[s->cur] : s->f[s->cur],
+                               (const uint32_t*)s->list_node.p,
                                (const int32_t*)s->list_slot.p, s->list_count,
                                (const double*)s->add_tab.p + (size_t)s->chunk_pos * nb, fa,
                                s->stream));
@@ -994,7 +1072,20 @@ int sc_fields(sc_sim* s, float* rho, float* u, double* totals)
 {
     TRY(check_usable(s));
     const FieldArgs fa = field_args(s);
-    if (rho || u) {
+    if ((rho || u) && s->two) {  // liquid density and the mixture's barycentric velocity
+        if (rho) TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
+        if (u) TRY(ensure(s, s->u_out, sizeof(float) * (size_t)s->N * s->d));
+        HIPX(launch_fields2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
+                             (double*)s->dens2.p, rho ? (float*)s->rho_out.p : nullptr, nullptr,
+                             u ? (float*)s->u_out.p : nullptr, step2c_args(s), s->stream));
+        if (rho)
+            HIPX(hipMemcpyAsync(rho, s->rho_out.p, sizeof(float) * (size_t)s->N,
+                                hipMemcpyDeviceToHost, s->stream));
+        if (u)
+            HIPX(hipMemcpyAsync(u, s->u_out.p, sizeof(float) * (size_t)s->N * s->d,
+                                hipMemcpyDeviceToHost, s->stream));
+        HIPX(hipStreamSynchronize(s->stream));
+    } else if (rho || u) {
         TRY(ensure(s, s->psi, sizeof(double) * (size_t)s->N));
         if (rho) TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
         if (u) TRY(ensure(s, s->u_out, sizeof(float) * (size_t)s->N * s->d));
@@ -1159,6 +1250,41 @@ int sc_film_geometry(sc_sim* s, int32_t nucleus_a, int32_t nucleus_b, double* h,
     return SC_OK;
 }
 
+int sc_gas_density(sc_sim* s, float* rho_v)
+{
+    TRY(check_usable(s));
+    if (!rho_v) return fail(SC_E_INVAL, "NULL output");
+    if (!s->two) {
+        std::memset(rho_v, 0, sizeof(float) * (size_t)s->N);
+        return SC_OK;
+    }
+    TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
+    HIPX(launch_fields2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
+                         (double*)s->dens2.p, nullptr, (float*)s->rho_out.p, nullptr,
+                         step2c_args(s), s->stream));
+    HIPX(hipMemcpyAsync(rho_v, s->rho_out.p, sizeof(float) * (size_t)s->N, hipMemcpyDeviceToHost,
+                        s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_set_gas_equilibrium(sc_sim* s, const double* rho_v)
+{
+    TRY(check_usable(s));
+    if (!s->two) return fail(SC_E_STATE, "no gas component (components = 1)");
+    if (!rho_v) return fail(SC_E_INVAL, "NULL density");
+    for (int64_t n = 0; n < s->N; ++n)
+        if (!(rho_v[n] > 0.0) || !std::isfinite(rho_v[n])) return fail(SC_E_INVAL, "rho_v must be finite and > 0");
+    TRY(ensure(s, s->tmp64, sizeof(double) * (size_t)s->N * 4));
+    double* rd = (double*)s->tmp64.p;
+    HIPX(hipMemcpyAsync(rd, rho_v, sizeof(double) * (size_t)s->N, hipMemcpyHostToDevice,
+                        s->stream));
+    HIPX(launch_set_eq(s->q, s->p.storage, s->fv[s->cur], init_args(s, 0.0), rd, nullptr,
+                       s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
 int sc_buoyancy_density(sc_sim* s, double* rho0)
 {
     TRY(check_usable(s));
@@ -1308,6 +1434,7 @@ int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int3
 {
     TRY(check_usable(s));
     if (trials < 1 || cap < 0 || (cap > 0 && !out)) return fail(SC_E_INVAL, "bad autotune arguments");
+    if (s->two) return fail(SC_E_UNSUPPORTED, "the two-component step has a single shape");
     StepArgs a = step_args(s);
     const std::vector<StepShape> cand = tune_candidates(s->q);
     hipEvent_t e0, e1;

@@ -44,6 +44,20 @@ bool step_shape_supported(int q, const StepShape& s);
 bool step_combo_supported(int storage, int compute);
 hipError_t launch_step(int q, int storage, int compute, const void* src, void* dst,
                        const StepArgs& a, const StepShape& s, hipStream_t st);
+// Two-component step (FP32 storage, FP64 arithmetic): densities of both components first, then
+// per node the cross forces, the common velocity and both collisions with streaming.
+struct Step2cArgs {
+    int nx, ny, nz;
+    int64_t N;
+    double tau_l, tau_v, Gx;
+};
+hipError_t launch_step2c(int q, const float* src_l, const float* src_v, float* dst_l,
+                         float* dst_v, double* dens /*[2][N]*/, const Step2cArgs& a,
+                         hipStream_t st);
+// Reported fields of the mixture: rho_l, rho_v (FP32) and the barycentric velocity.
+hipError_t launch_fields2c(int q, const float* f_l, const float* f_v, double* dens, float* rho_l,
+                           float* rho_v, float* u, const Step2cArgs& a, hipStream_t st);
+
 // Barrier fix-up of the listed frontier nodes after a step (same src/dst as that step).
 hipError_t launch_barrier_fix(int q, int storage, int compute, const void* src, void* dst,
                               const StepArgs& a, const uint32_t* list, int count, hipStream_t st);
@@ -77,6 +91,10 @@ struct FieldArgs {
     double psi_ld;
     int grav;               // gravity body force (rho - rho0) g in the reported velocity
     double gd[3], rho0d;
+    // two-component mode: the gas component's populations (null: one component) and the cross
+    // interaction; pressures then follow p = (rho_l + rho_v)/3 + (Gx/3) rho_l rho_v
+    const void* f2;
+    double Gx;
 };
 hipError_t launch_psi(int q, int storage, const void* f, double* psi, const FieldArgs& a,
                       hipStream_t st);

@@ -67,6 +67,19 @@ __device__ __forceinline__ double rho_d(const S* f, int64_t n, const FieldArgs& 
     return a.rho_ref_d + s;
 }
 
+// EOS pressure at node n: one component, p = rho/3 + (G/6) psi^2; two components (the gas
+// component in a.f2, FP32), p = (rho_l + rho_v)/3 + (Gx/3) rho_l rho_v.
+template <int Q, typename S>
+__device__ __forceinline__ double pressure_at(const S* f, int64_t n, const FieldArgs& a)
+{
+    const double r = rho_d<Q, S>(f, n, a);
+    if (a.f2) {
+        const double rv = rho_d<Q, float>((const float*)a.f2, n, a);
+        return (r + rv) / 3.0 + (a.Gx / 3.0) * r * rv;
+    }
+    return pressure_d(r, a.Gd);
+}
+
 // ---- psi and the reported fields (FP64 arithmetic, FP32 output) -------------------------------
 template <int Q, typename S>
 __global__ void k_psi(const S* f, double* psi, FieldArgs a)
@@ -131,7 +144,7 @@ __global__ void k_pressure(const S* f, double* p, FieldArgs a)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
          n += (int64_t)gridDim.x * blockDim.x)
-        p[n] = pressure_d(rho_d<Q, S>(f, n, a), a.Gd);
+        p[n] = pressure_at<Q, S>(f, n, a);
 }
 
 template <int Q>
@@ -418,11 +431,11 @@ __global__ void k_merge(const S* f, const uint32_t* labels, const MergePair* pai
         if (clean) {
             int x, y, z;
             coords3(cstar, a.nx, a.ny, x, y, z);
-            const double pc = pressure_d(best, a.Gd);
+            const double pc = pressure_at<Q, S>(f, cstar, a);
             double acc = 0.0;
             for (int i = 1; i < Q; ++i) {
                 const int64_t m = shifted<Q>(x, y, z, i, +1, a);
-                acc += L::wd[i] * (pressure_d(rho_d<Q, S>(f, m, a), a.Gd) - pc);
+                acc += L::wd[i] * (pressure_at<Q, S>(f, m, a) - pc);
             }
             const double lap = 6.0 * acc;
             r.film_len = len;

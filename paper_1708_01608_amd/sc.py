@@ -46,6 +46,8 @@ class Params(C.Structure):
         ("step_variant", C.c_int32),
         ("barrier", C.c_int32), ("corona", C.c_int32),
         ("gravity", C.c_double * 3), ("rho_buoyancy", C.c_double),
+        ("components", C.c_int32), ("reserved2", C.c_int32), ("G_cross", C.c_double),
+        ("tau_vapour", C.c_double), ("rho_vapour", C.c_double), ("rho_dissolved", C.c_double),
     ]
 
 
@@ -96,7 +98,7 @@ class BatchResult(C.Structure):
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
     "sc_seed_nuclei", "sc_step", "sc_fields", "sc_laplacian_p", "sc_label_bubbles",
-    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_time",
+    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density", "sc_set_gas_equilibrium", "sc_time",
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
@@ -140,6 +142,8 @@ def load_library(path=LIB_PATH):
         "sc_owner": (C.c_int, [P, P]),
         "sc_buoyancy_density": (C.c_int, [P, P]),
         "sc_film_geometry": (C.c_int, [P, C.c_int32, C.c_int32, P, P, P]),
+        "sc_gas_density": (C.c_int, [P, P]),
+        "sc_set_gas_equilibrium": (C.c_int, [P, P]),
         "sc_time": (C.c_int, [P, P]),
         "sc_lattice": (C.c_int, [C.c_int32, P, P]),
         "sc_get_populations": (C.c_int, [P, P]),
@@ -210,8 +214,14 @@ class TorchMemory:
             except Exception:  # allocation failure is reported to the library as NULL
                 return None
 
+        delete = torch.cuda.caching_allocator_delete
+
         def _free(ptr, user):
-            torch.cuda.caching_allocator_delete(ptr)
+            # at interpreter exit a handle may outlive torch's CUDA state: nothing to return
+            try:
+                delete(ptr)
+            except Exception:
+                pass
 
         self._alloc = ALLOC_FN(_alloc)
         self._free = FREE_FN(_free)
@@ -238,7 +248,7 @@ class Sim:
     def __init__(self, q=9, nx=128, ny=128, nz=1, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16,
                  amp=1e-3, seed=1, theta=0.0, K=10, film_max=8, storage="f32", compute="auto",
                  rho_ref=-1.0, tile=None, variant=0, memory="torch", tuned=True, barrier=False,
-                 corona=3, gravity=None, rho0=0.0):
+                 corona=3, gravity=None, rho0=0.0, two_component=None):
         self._lib = load_library()
         self._h = None
         p = Params()
@@ -263,6 +273,10 @@ class Sim:
             for c, v in enumerate(gravity):
                 p.gravity[c] = float(v)
         p.rho_buoyancy = float(rho0)
+        if two_component is not None:  # (G_cross, tau_vapour, rho_vapour, rho_dissolved)
+            p.components = 2
+            p.G_cross, p.tau_vapour, p.rho_vapour, p.rho_dissolved = [float(v) for v in
+                                                                       two_component]
         self.mem = None
         if memory == "torch":
             self.mem = TorchMemory()
@@ -337,6 +351,16 @@ class Sim:
         nc = C.c_int64()
         _check(self._lib.sc_label_bubbles(self._h, _ptr(m), _ptr(lab), C.byref(nc)))
         return lab, nc.value
+
+    def gas_density(self):
+        """Density of the gas component (two-component mode; zeros otherwise)."""
+        r = np.zeros(self.N, dtype=np.float32)
+        _check(self._lib.sc_gas_density(self._h, _ptr(r)))
+        return r
+
+    def set_gas_equilibrium(self, rho_v):
+        r = np.ascontiguousarray(rho_v, dtype=np.float64).reshape(self.N)
+        _check(self._lib.sc_set_gas_equilibrium(self._h, _ptr(r)))
 
     def film_geometry(self, a, b):
         """(h, R_d, n_lines) of the bubbles holding nuclei a and b at the last test pass."""

@@ -122,6 +122,22 @@ def test_gravity_parameters_are_checked(lib, g, storage, variant, code):
     assert not h.value
 
 
+@pytest.mark.parametrize("field,value,code", [
+    ("components", 3, sc.SC_E_INVAL), ("rho_vapour", 0.0, sc.SC_E_INVAL),
+    ("tau_vapour", 0.5, sc.SC_E_INVAL), ("storage", 1, sc.SC_E_UNSUPPORTED),
+    ("compute", 1, sc.SC_E_UNSUPPORTED), ("barrier", 1, sc.SC_E_UNSUPPORTED),
+])
+def test_two_component_parameters_are_checked(lib, field, value, code):
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    assert p.components == 1 and p.G_cross == 1.5 and p.rho_dissolved == 0.05
+    p.components = 2
+    setattr(p, field, value)
+    h = C.c_void_p()
+    assert lib.sc_create(C.byref(p), C.byref(h)) == code
+    assert not h.value
+
+
 def test_boxes_past_32bit_byte_offsets_are_rejected(lib):
     # 1024 x 1024 x 1025 FP32 values need byte offsets past 2^32
     p = sc.Params()

@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("foam_3d", "foam_2d", "two_bubble", "foam_3d_large", "batch")
+WORKLOADS = ("foam_3d", "foam_2d", "two_bubble", "foam_3d_large", "batch", "mixture_2d",
+             "mixture_3d")
 
 
 def parse():
@@ -58,11 +59,13 @@ def workload_spec(name):
     from paper_1708_01608_amd import workloads as W
 
     return {"foam_3d": W.foam_3d, "foam_2d": W.foam_2d, "two_bubble": W.two_bubble,
-            "foam_3d_large": W.foam_3d_large}[name]()
+            "foam_3d_large": W.foam_3d_large, "mixture_2d": W.mixture_2d,
+            "mixture_3d": W.mixture_3d}[name]()
 
 
-def bytes_per_node(q, storage):
-    return 2 * q * (4 if storage == "f32" else 2)
+def bytes_per_node(q, storage, components=1):
+    """Algorithmic bytes per node and step: every population read once and written once."""
+    return components * 2 * q * (4 if storage == "f32" else 2)
 
 
 def kernel_hash(files=("sc_step.hip", "sc_stepcore.hpp", "sc_device.hpp")):
@@ -75,6 +78,10 @@ def kernel_hash(files=("sc_step.hip", "sc_stepcore.hpp", "sc_device.hpp")):
 
 def step_kernel_hash():
     return kernel_hash()
+
+
+def mixture_kernel_hash():
+    return kernel_hash(("sc_step2c.hip", "sc_stepcore.hpp", "sc_device.hpp"))
 
 
 def batch_kernel_hash():
@@ -103,7 +110,8 @@ def traffic_from_profile(workload, storage, compute, tile):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_hash") != step_kernel_hash() or list(d.get("tile", [])) != list(tile):
+    h = mixture_kernel_hash() if workload.startswith("mixture") else step_kernel_hash()
+    if d.get("kernel_hash") != h or list(d.get("tile", [])) != list(tile):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -146,7 +154,8 @@ def cpu_baseline(spec, sample_steps):
     from oracle import OracleSim, num_threads
 
     o = OracleSim(spec.q, spec.nx, spec.ny, spec.nz, spec.tau, spec.G, spec.rho_l, spec.rho_g,
-                  spec.amp, spec.seed, spec.theta, 0, spec.film_max)
+                  spec.amp, spec.seed, spec.theta, 0, spec.film_max,
+                  two_component=spec.two_component)
     o.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
     if sample_steps <= 0:
         t0 = time.perf_counter()
@@ -271,12 +280,16 @@ def main():
         run_batch(args)
         return
     spec = workload_spec(args.workload)
+    comps = 1 if spec.two_component is None else 2
+    if comps == 2 and (args.barrier or args.storage != "f32" or args.compute == "f32"):
+        print(json.dumps({"error": "the mixture runs on FP32 storage, FP64 arithmetic, no barrier"}))
+        sys.exit(2)
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     r = run_gpu(spec, args, args.storage, args.compute, args.steps, args.warmup, tile)
     lattice_steps = args.steps * spec.K
     mlups = spec.N * lattice_steps / r["wall"] / 1e6
     # the barrier adds the 2-byte owner id each node reads
-    bpn = bytes_per_node(spec.q, args.storage) + (2 if args.barrier else 0)
+    bpn = bytes_per_node(spec.q, args.storage, comps) + (2 if args.barrier else 0)
     bytes_per_launch = bpn * spec.N
     avg_s = r["step_ms"] / 1e3 / max(r["launches"], 1)
     achieved = bytes_per_launch / avg_s / 1e9
@@ -309,6 +322,7 @@ def main():
             "lattice_steps_per_step": spec.K,
             "step_tile": list(r["tile"]),
             "barrier": bool(args.barrier),
+            "components": comps,
             "shape_source": ("--tile" if args.tile else "autotune" if args.autotune
                              else "tuned_shapes.json or default"),
         },
@@ -319,7 +333,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_step3d" if spec.q == 19 else "k_step2d",
+            "kernel": ("k_mix" if comps == 2 else "k_step") + ("3d" if spec.q == 19 else "2d"),
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(avg_s * 1e6, 2),
             "launches": r["launches"],
@@ -340,7 +354,7 @@ def main():
     print(json.dumps(out), flush=True)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
-    if args.variants:
+    if args.variants and comps == 1:
         for storage, compute in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
             if args.barrier and storage != "f32":
                 continue  # the barrier runs on FP32 storage only

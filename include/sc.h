@@ -112,7 +112,10 @@ typedef struct sc_params {
      * p = (rho_l + rho_v)/3 + (G_cross/3) rho_l rho_v; totals sum both components; sc_fields
      * reports the liquid density and the mixture's barycentric velocity
      * (j_l + j_v + (F_l + F_v)/2) / (rho_l + rho_v); population access concerns the liquid.
-     * FP32 storage and FP64 arithmetic only, no barrier, no gravity (SC_E_UNSUPPORTED). */
+     * FP32 storage with rho_ref <= 0 (unshifted) and FP64 arithmetic only, no barrier, no
+     * gravity (SC_E_UNSUPPORTED).  The step is one fused kernel for both components; its tiles
+     * are D2Q9 tile_x in {64, 128, 256, 512}, D3Q19 (tile_x, tile_y) in {(32,4), (32,8), (64,4),
+     * (64,8), (128,4)}, any tile_z >= 1 planes, step_variant 1 or 3 (SC_E_INVAL otherwise). */
     int32_t components;        /* 1 (default) or 2 */
     int32_t reserved2;
     double G_cross;            /* cross interaction, > 0 repels (default 1.5) */
@@ -252,8 +255,8 @@ int sc_profile_read(struct sc_sim* sim, int32_t kernel_class, double* ms, int64_
 /* Autotuner of the step kernel.  Times every candidate (tile_x, tile_y, tile_z, variant) on the
  * current state with HIP events -- each trial launch reads the current populations and writes the
  * spare buffer, so the simulation is unchanged -- and keeps the fastest for this handle.  The
- * choice is remembered for later handles of the same lattice, box, storage and compute type in
- * this process.  trials >= 1 launches per candidate; out[cap] (may be NULL) receives the timings
+ * choice is remembered for later handles of the same lattice, box, storage, compute type and
+ * component count in this process (two components tune their own fused kernel's shapes).  trials >= 1 launches per candidate; out[cap] (may be NULL) receives the timings
  * in candidate order, *n_out the candidate count. */
 typedef struct sc_tune_entry {
     int32_t tile_x, tile_y, tile_z, variant;

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsc.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["sc_step.hip", "sc_test.hip", "sc_batch.hip", "sc_probe.hip", "sc_api.hip"]
+SOURCES = ["sc_step.hip", "sc_step2c.hip", "sc_test.hip", "sc_batch.hip", "sc_probe.hip", "sc_api.hip"]
 ARCH = os.environ.get("SC_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -198,6 +198,7 @@ Step2cArgs step2c_args(const sc_sim* s)
     Step2cArgs a;
     a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
     a.N = s->N;
+    a.planes = s->shape.tile_z;
     a.tau_l = s->p.tau;
     a.tau_v = s->tau_v;
     a.Gx = s->p.G_cross;
@@ -261,14 +262,15 @@ StepShape default_shape(const sc_params& p)
     return sh;
 }
 
-// Shapes chosen by sc_autotune, per (lattice, nx, ny, nz, storage, compute), for this process.
-using TuneKey = std::tuple<int, int, int, int, int, int>;
+// Shapes chosen by sc_autotune, per (lattice, nx, ny, nz, storage, compute, components), for
+// this process.
+using TuneKey = std::tuple<int, int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, StepShape> g_tuned;
 
 TuneKey tune_key(const sc_params& p, int compute)
 {
-    return TuneKey{p.lattice, p.nx, p.ny, p.nz, p.storage, compute};
+    return TuneKey{p.lattice, p.nx, p.ny, p.nz, p.storage, compute, p.components};
 }
 
 std::vector<StepShape> tune_candidates(int q)
@@ -283,6 +285,22 @@ std::vector<StepShape> tune_candidates(int q)
         for (auto& t : tiles)
             for (int tz : {16, 32, 64})
                 for (int v : {1, 2, 3}) c.push_back(StepShape{t[0], t[1], tz, v});
+    }
+    return c;
+}
+
+std::vector<StepShape> tune_candidates_2c(int q)
+{
+    std::vector<StepShape> c;
+    if (q == SC_D2Q9) {
+        for (int tx : {64, 128, 256, 512})
+            for (int tz : {2, 4, 8, 16, 32, 64})
+                for (int v : {1, 3}) c.push_back(StepShape{tx, 1, tz, v});
+    } else {
+        const int tiles[][2] = {{32, 4}, {32, 8}, {64, 4}, {64, 8}, {128, 4}};
+        for (auto& t : tiles)
+            for (int tz : {16, 32, 64})
+                for (int v : {1, 3}) c.push_back(StepShape{t[0], t[1], tz, v});
     }
     return c;
 }
@@ -786,6 +804,8 @@ int validate(const sc_params* p)
             return fail(SC_E_INVAL, "tau_vapour must be > 0.5 (or <= 0 for tau)");
         if (p->storage != SC_STORE_F32 || p->compute == SC_COMPUTE_F32)
             return fail(SC_E_UNSUPPORTED, "two components run on FP32 storage, FP64 arithmetic");
+        if (p->rho_ref > 0.0)
+            return fail(SC_E_UNSUPPORTED, "two components store unshifted populations (rho_ref <= 0)");
         if (p->barrier) return fail(SC_E_UNSUPPORTED, "no barrier with two components");
         if (p->gravity[0] != 0.0 || p->gravity[1] != 0.0 || p->gravity[2] != 0.0)
             return fail(SC_E_UNSUPPORTED, "no gravity with two components");
@@ -805,7 +825,9 @@ int validate(const sc_params* p)
         return fail(SC_E_INVAL, "allocator needs alloc and free");
     if (p->tile_x || p->tile_y || p->tile_z || p->step_variant) {
         StepShape sh = shape_from_params(*p);
-        if (!step_shape_supported(p->lattice, sh)) return fail(SC_E_INVAL, "unsupported step tile");
+        const bool ok = p->components == 2 ? step2c_shape_supported(p->lattice, sh)
+                                           : step_shape_supported(p->lattice, sh);
+        if (!ok) return fail(SC_E_INVAL, "unsupported step tile");
     }
     return SC_OK;
 }
@@ -1029,7 +1051,7 @@ int sc_step(sc_sim* s, int32_t nsteps)
         if (s->two)
             HIPX(launch_step2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
                                (float*)s->f[s->cur ^ 1], (float*)s->fv[s->cur ^ 1],
-                               (double*)s->dens2.p, step2c_args(s), s->stream));
+                               step2c_args(s), s->shape, s->stream));
         else
             HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a,
                              s->shape, s->stream));
@@ -1434,9 +1456,19 @@ int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int3
 {
     TRY(check_usable(s));
     if (trials < 1 || cap < 0 || (cap > 0 && !out)) return fail(SC_E_INVAL, "bad autotune arguments");
-    if (s->two) return fail(SC_E_UNSUPPORTED, "the two-component step has a single shape");
     StepArgs a = step_args(s);
-    const std::vector<StepShape> cand = tune_candidates(s->q);
+    const Step2cArgs a2 = step2c_args(s);
+    const std::vector<StepShape> cand = s->two ? tune_candidates_2c(s->q) : tune_candidates(s->q);
+    // one step current -> spare buffers (the state itself is left as it is)
+    auto launch = [&](const StepShape& sh) {
+        if (s->two)
+            return launch_step2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
+                                 (float*)s->f[s->cur ^ 1], (float*)s->fv[s->cur ^ 1], a2, sh,
+                                 s->stream);
+        a.planes = sh.tile_z;
+        return launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a, sh,
+                           s->stream);
+    };
     hipEvent_t e0, e1;
     HIPX(hipEventCreate(&e0));
     HIPX(hipEventCreate(&e1));
@@ -1445,16 +1477,12 @@ int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int3
     int k = 0;
     int rc = SC_OK;
     for (const StepShape& sh : cand) {
-        if (!step_shape_supported(s->q, sh)) continue;
+        if (!(s->two ? step2c_shape_supported(s->q, sh) : step_shape_supported(s->q, sh))) continue;
         if (s->grav && sh.variant == 2) continue;  // no pipelined gravity kernel
-        a.planes = sh.tile_z;
-        // one untimed launch, then `trials` timed launches current -> spare buffer
-        hipError_t e = launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1],
-                                   a, sh, s->stream);
+        // one untimed launch, then `trials` timed launches
+        hipError_t e = launch(sh);
         if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
-        for (int r = 0; r < trials && e == hipSuccess; ++r)
-            e = launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a, sh,
-                            s->stream);
+        for (int r = 0; r < trials && e == hipSuccess; ++r) e = launch(sh);
         if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;

@@ -44,17 +44,22 @@ bool step_shape_supported(int q, const StepShape& s);
 bool step_combo_supported(int storage, int compute);
 hipError_t launch_step(int q, int storage, int compute, const void* src, void* dst,
                        const StepArgs& a, const StepShape& s, hipStream_t st);
-// Two-component step (FP32 storage, FP64 arithmetic): densities of both components first, then
-// per node the cross forces, the common velocity and both collisions with streaming.
+// --- two-component kernels (sc_step2c.hip) ---------------------------------------------------
+// Two-component step (FP32 unshifted storage, FP64 arithmetic): one fused marching kernel per
+// step (both densities over the tile and its ring in LDS, the cross forces, the common velocity,
+// both collisions with streaming).  Shapes: tile_x, tile_y, planes = tile_z, variant 1 or 3
+// (non-temporal stores).
 struct Step2cArgs {
     int nx, ny, nz;
+    int planes;  // set by launch_step2c from the shape
     int64_t N;
     double tau_l, tau_v, Gx;
 };
+bool step2c_shape_supported(int q, const StepShape& s);
 hipError_t launch_step2c(int q, const float* src_l, const float* src_v, float* dst_l,
-                         float* dst_v, double* dens /*[2][N]*/, const Step2cArgs& a,
-                         hipStream_t st);
-// Reported fields of the mixture: rho_l, rho_v (FP32) and the barycentric velocity.
+                         float* dst_v, const Step2cArgs& a, const StepShape& s, hipStream_t st);
+// Reported fields of the mixture: rho_l, rho_v (FP32) and the barycentric velocity; dens holds
+// [2][N] FP64 densities afterwards.
 hipError_t launch_fields2c(int q, const float* f_l, const float* f_v, double* dens, float* rho_l,
                            float* rho_v, float* u, const Step2cArgs& a, hipStream_t st);
 

@@ -27,22 +27,6 @@ namespace sc {
 
 size_t storage_bytes(int storage) { return storage == SC_STORE_F32 ? 4 : 2; }
 
-struct StepGrid {
-    int gx, gy, gz;  // tiles along x, y and plane chunks
-    int remap;       // 1: contiguous tile ranges per XCD (8 XCDs, round-robin dispatch)
-};
-
-// Logical tile of this block.  Blocks are dispatched round-robin over the 8 XCDs, so block b
-// runs on XCD b % 8; with remap, XCD k processes the contiguous logical range
-// [k * n/8, (k+1) * n/8) and neighbouring tiles share that XCD's L2.
-__device__ __forceinline__ int logical_block(const StepGrid& g)
-{
-    const int b = blockIdx.x;
-    const int n = g.gx * g.gy * g.gz;
-    if (!g.remap) return b;
-    return (b & 7) * (n >> 3) + (b >> 3);
-}
-
 // ------------------------------------------------------------------------------------------
 // D2Q9: a block owns TX nodes of a row and marches `planes` rows in y.
 // ------------------------------------------------------------------------------------------
@@ -446,181 +430,6 @@ hipError_t launch_barrier_fix(int q, int storage, int compute, const void* src, 
         else { if (g) SC_FIX(19, float, true); else SC_FIX(19, float, false); }
     }
 #undef SC_FIX
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------------------
-// Two components (liquid l, gas v; Shan-Doolen mixture with psi = rho): the force on component
-// a is -Gx rho_a(x) sum_i w_i rho_b(x + e_i) e_i; both relax to equilibria at the common
-// velocity u' = sum_a (j_a / tau_a) / sum_a (rho_a / tau_a) shifted by tau_a F_a / rho_a.  A
-// first pass stores both densities (FP64); the step pulls both components, reads the
-// neighbours' densities from that field and hands each component to the one-component
-// collision with the force F_a + (rho_a u' - j_a) / tau_a, whose equilibrium velocity is then
-// exactly u' + tau_a F_a / rho_a.
-// ------------------------------------------------------------------------------------------
-template <int Q>
-__device__ __forceinline__ void pull_at(const float* src, int64_t N, int nx, int ny, int nz,
-                                        int64_t n, float* g)
-{
-    const int x = (int)(n % nx);
-    const int64_t r = n / nx;
-    const int y = (int)(r % ny), z = (int)(r / ny);
-    pull_node<Q>(src, N, nx, ny, x, wrap_once(x - 1, nx), wrap_once(x + 1, nx), y,
-                 wrap_once(y - 1, ny), wrap_once(y + 1, ny), z,
-                 Q == 19 ? wrap_once(z - 1, nz) : 0, Q == 19 ? wrap_once(z + 1, nz) : 0, g);
-}
-
-template <int Q>
-__global__ void __launch_bounds__(256) k_dens2c(const float* __restrict__ fl,
-                                                const float* __restrict__ fv,
-                                                double* __restrict__ dens, Step2cArgs a)
-{
-    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        float g[Q];
-        pull_at<Q>(fl, a.N, a.nx, a.ny, a.nz, n, g);
-        dens[n] = sum_dev<Q, double>(g);
-        pull_at<Q>(fv, a.N, a.nx, a.ny, a.nz, n, g);
-        dens[a.N + n] = sum_dev<Q, double>(g);
-    }
-}
-
-// Node n + e_i, periodic.
-template <int Q>
-__device__ __forceinline__ int64_t node_plus(int x, int y, int z, int i, const Step2cArgs& a)
-{
-    using L = lat<Q>;
-    return wrap_once(x + L::ex[i], a.nx) +
-           (int64_t)a.nx * (wrap_once(y + L::ey[i], a.ny) +
-                            (int64_t)a.ny * (Q == 19 ? wrap_once(z + L::ez[i], a.nz) : 0));
-}
-
-template <int Q>
-__device__ __forceinline__ void momentum(const float* g, double j[3])
-{
-    using L = lat<Q>;
-    j[0] = j[1] = j[2] = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (L::ex[i] > 0) j[0] += (double)g[i]; else if (L::ex[i] < 0) j[0] -= (double)g[i];
-        if (L::ey[i] > 0) j[1] += (double)g[i]; else if (L::ey[i] < 0) j[1] -= (double)g[i];
-        if (L::ez[i] > 0) j[2] += (double)g[i]; else if (L::ez[i] < 0) j[2] -= (double)g[i];
-    }
-}
-
-template <int Q>
-__global__ void __launch_bounds__(256) k_step2c(const float* __restrict__ sl,
-                                                const float* __restrict__ sv,
-                                                float* __restrict__ dl, float* __restrict__ dv,
-                                                const double* __restrict__ dens, Step2cArgs a)
-{
-    const double* __restrict__ rl_f = dens;
-    const double* __restrict__ rv_f = dens + a.N;
-    const Coef<double> cl{a.tau_l, 1.0 / a.tau_l, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0};
-    const Coef<double> cv{a.tau_v, 1.0 / a.tau_v, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0};
-    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % a.nx);
-        const int64_t r = n / a.nx;
-        const int y = (int)(r % a.ny), z = (int)(r / a.ny);
-        float gl[Q], gv[Q];
-        pull_at<Q>(sl, a.N, a.nx, a.ny, a.nz, n, gl);
-        pull_at<Q>(sv, a.N, a.nx, a.ny, a.nz, n, gv);
-        const double rl = sum_dev<Q, double>(gl), rv = sum_dev<Q, double>(gv);
-        double sx, sy, sz, tx, ty, tz;
-        interaction_sum<Q, double>([&](int i) { return rv_f[node_plus<Q>(x, y, z, i, a)]; },
-                                   sx, sy, sz);
-        interaction_sum<Q, double>([&](int i) { return rl_f[node_plus<Q>(x, y, z, i, a)]; },
-                                   tx, ty, tz);
-        const double Fl[3] = {-a.Gx * rl * sx, -a.Gx * rl * sy, -a.Gx * rl * sz};
-        const double Fv[3] = {-a.Gx * rv * tx, -a.Gx * rv * ty, -a.Gx * rv * tz};
-        double jl[3], jv[3];
-        momentum<Q>(gl, jl);
-        momentum<Q>(gv, jv);
-        const double den = rl / a.tau_l + rv / a.tau_v;
-        double el[3], ev[3];
-        for (int c = 0; c < 3; ++c) {
-            const double up = (jl[c] / a.tau_l + jv[c] / a.tau_v) / den;
-            el[c] = Fl[c] + (rl * up - jl[c]) / a.tau_l;
-            ev[c] = Fv[c] + (rv * up - jv[c]) / a.tau_v;
-        }
-        collide_store<Q, double, float>(dl, a.N, (uint32_t)n, gl, rl, el[0], el[1],
-                                        Q == 19 ? el[2] : 0.0, cl);
-        collide_store<Q, double, float>(dv, a.N, (uint32_t)n, gv, rv, ev[0], ev[1],
-                                        Q == 19 ? ev[2] : 0.0, cv);
-    }
-}
-
-template <int Q>
-__global__ void __launch_bounds__(256) k_fields2c(const float* __restrict__ fl,
-                                                  const float* __restrict__ fv,
-                                                  const double* __restrict__ dens, float* rl_out,
-                                                  float* rv_out, float* u_out, Step2cArgs a)
-{
-    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        const double rl = dens[n], rv = dens[a.N + n];
-        if (rl_out) rl_out[n] = (float)rl;
-        if (rv_out) rv_out[n] = (float)rv;
-        if (!u_out) continue;
-        const int x = (int)(n % a.nx);
-        const int64_t r = n / a.nx;
-        const int y = (int)(r % a.ny), z = (int)(r / a.ny);
-        float gl[Q], gv[Q];
-        pull_at<Q>(fl, a.N, a.nx, a.ny, a.nz, n, gl);
-        pull_at<Q>(fv, a.N, a.nx, a.ny, a.nz, n, gv);
-        double sx, sy, sz, tx, ty, tz, jl[3], jv[3];
-        interaction_sum<Q, double>([&](int i) { return dens[a.N + node_plus<Q>(x, y, z, i, a)]; },
-                                   sx, sy, sz);
-        interaction_sum<Q, double>([&](int i) { return dens[node_plus<Q>(x, y, z, i, a)]; },
-                                   tx, ty, tz);
-        momentum<Q>(gl, jl);
-        momentum<Q>(gv, jv);
-        const double S[3] = {rl * sx + rv * tx, rl * sy + rv * ty, rl * sz + rv * tz};
-        for (int c = 0; c < lat<Q>::d; ++c)  // (j_l + j_v + (F_l + F_v)/2) / (rho_l + rho_v)
-            u_out[(int64_t)c * a.N + n] = (float)((jl[c] + jv[c] - 0.5 * a.Gx * S[c]) / (rl + rv));
-    }
-}
-
-static dim3 grid_nodes(int64_t N)
-{
-    int64_t b = (N + 255) / 256;
-    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 16)));
-}
-
-hipError_t launch_step2c(int q, const float* src_l, const float* src_v, float* dst_l,
-                         float* dst_v, double* dens, const Step2cArgs& a, hipStream_t st)
-{
-    const dim3 grid = grid_nodes(a.N);
-    if (q == 9) {
-        hipLaunchKernelGGL((k_dens2c<9>), grid, dim3(256), 0, st, src_l, src_v, dens, a);
-        hipLaunchKernelGGL((k_step2c<9>), grid, dim3(256), 0, st, src_l, src_v, dst_l, dst_v,
-                           dens, a);
-    } else if (q == 19) {
-        hipLaunchKernelGGL((k_dens2c<19>), grid, dim3(256), 0, st, src_l, src_v, dens, a);
-        hipLaunchKernelGGL((k_step2c<19>), grid, dim3(256), 0, st, src_l, src_v, dst_l, dst_v,
-                           dens, a);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_fields2c(int q, const float* f_l, const float* f_v, double* dens, float* rho_l,
-                           float* rho_v, float* u, const Step2cArgs& a, hipStream_t st)
-{
-    const dim3 grid = grid_nodes(a.N);
-    if (q == 9) {
-        hipLaunchKernelGGL((k_dens2c<9>), grid, dim3(256), 0, st, f_l, f_v, dens, a);
-        hipLaunchKernelGGL((k_fields2c<9>), grid, dim3(256), 0, st, f_l, f_v, dens, rho_l,
-                           rho_v, u, a);
-    } else if (q == 19) {
-        hipLaunchKernelGGL((k_dens2c<19>), grid, dim3(256), 0, st, f_l, f_v, dens, a);
-        hipLaunchKernelGGL((k_fields2c<19>), grid, dim3(256), 0, st, f_l, f_v, dens, rho_l,
-                           rho_v, u, a);
-    } else {
-        return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 

@@ -1,11 +1,28 @@
-// sc_stepcore.hpp -- per-node pieces of the Shan-Chen step shared by the single-box and the
-// batched kernels: pulled loads, deviation sums, and the forced BGK collision.
+// sc_stepcore.hpp -- pieces of the Shan-Chen step shared by the step kernels (one and two
+// components) and the batched kernel: the XCD-aware tile order, pulled loads, deviation sums,
+// the grouped interaction sum and the forced BGK collision.
 #pragma once
 
 #include "sc_device.hpp"
 #include "sc_internal.hpp"
 
 namespace sc {
+
+struct StepGrid {
+    int gx, gy, gz;  // tiles along x, y and plane chunks
+    int remap;       // 1: contiguous tile ranges per XCD (8 XCDs, round-robin dispatch)
+};
+
+// Logical tile of this block.  Blocks are dispatched round-robin over the 8 XCDs, so block b
+// runs on XCD b % 8; with remap, XCD k processes the contiguous logical range
+// [k * n/8, (k+1) * n/8) and neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int logical_block(const StepGrid& g)
+{
+    const int b = blockIdx.x;
+    const int n = g.gx * g.gy * g.gz;
+    if (!g.remap) return b;
+    return (b & 7) * (n >> 3) + (b >> 3);
+}
 
 // Pulled populations g_i = stored_i(x - e_i) of one node: unsigned 32-bit byte offsets from a
 // per-direction base, so one vector add per load and the 64-bit bases stay in scalar registers.
@@ -144,8 +161,34 @@ __device__ __forceinline__ A e_dot(int i, A ux, A uy, A uz)
     return s;
 }
 
-// The stored population i of node `lane` is written at byte offset lane sizeof(S) from the
-// direction's base dst + i N (below 2^32, as for the loads).
+// BGK relaxation towards f^eq(rho, u_eq) and the store of node `lane`:
+// g_i* = g_i + omega (f_i^eq - f_i), written as deviations (the stored shift cancels in the
+// difference: f_i - f_i^eq = g_i - (w_i drho + w_i rho P_i)).  Population i goes to byte offset
+// lane sizeof(S) from the direction's base dst + i N (below 2^32, as for the loads).
+template <int Q, typename A, typename S, bool NT = false>
+__device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint32_t lane,
+                                            const float* g, A drho, A rho, A ux, A uy, A uz,
+                                            A omega)
+{
+    constexpr bool three = Q == 19;
+    const A usq15 = (A)1.5 * (three ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy);
+    const uint32_t boff = lane * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const A eu = e_dot<Q, A>(i, ux, uy, uz);
+        const A P = fmad(eu, fmad((A)4.5, eu, (A)3), -usq15);
+        const A w = weight<Q, A>(i);
+        const A gi = (A)g[i];
+        const A h = fmad(-w, drho, gi);
+        const A d = fmad(w * rho, P, -h);
+        const A gs = fmad(omega, d, gi);
+        char* base = reinterpret_cast<char*>(dst + (int64_t)i * N);
+        put<NT, S>(reinterpret_cast<S*>(base + boff), store_f<S>((float)gs));
+    }
+}
+
+// Forced collision of one component: velocity-shift forcing u_eq = (j + tau F) / rho, then the
+// BGK relaxation and the store.
 template <int Q, typename A, typename S, bool NT = false, bool EXT = false>
 __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, uint32_t lane,
                                               const float* g, A drho, A Fx, A Fy, A Fz,
@@ -174,20 +217,7 @@ __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, ui
     const A ux = fmad(c.tau, Fx, jx) * inv;
     const A uy = fmad(c.tau, Fy, jy) * inv;
     const A uz = three ? fmad(c.tau, Fz, jz) * inv : (A)0;
-    const A usq15 = (A)1.5 * (three ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy);
-    const uint32_t boff = lane * (uint32_t)sizeof(S);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const A eu = e_dot<Q, A>(i, ux, uy, uz);
-        const A P = fmad(eu, fmad((A)4.5, eu, (A)3), -usq15);
-        const A w = weight<Q, A>(i);
-        const A gi = (A)g[i];
-        const A h = fmad(-w, drho, gi);
-        const A d = fmad(w * rho, P, -h);
-        const A gs = fmad(c.omega, d, gi);
-        char* base = reinterpret_cast<char*>(dst + (int64_t)i * N);
-        put<NT, S>(reinterpret_cast<S*>(base + boff), store_f<S>((float)gs));
-    }
+    relax_store<Q, A, S, NT>(dst, N, lane, g, drho, rho, ux, uy, uz, c.omega);
 }
 
 }  // namespace sc

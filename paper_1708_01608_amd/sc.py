@@ -228,7 +228,7 @@ class TorchMemory:
         self.struct = Allocator(self._alloc, self._free, None)
 
 
-def _tuned_shape(q, nx, ny, nz, storage, compute, variant):
+def _tuned_shape(q, nx, ny, nz, storage, compute, variant, components=1):
     """Step-kernel shape stored by paper_1708_01608_amd.tune for this box, if any."""
     from . import tune
 
@@ -236,7 +236,7 @@ def _tuned_shape(q, nx, ny, nz, storage, compute, variant):
     comp = compute
     if comp == "auto":
         comp = "f64" if st == "f32" else "f32"
-    e = tune.load().get(tune.key(q, nx, ny, nz, st, comp))
+    e = tune.load().get(tune.key(q, nx, ny, nz, st, comp, components))
     if not e:
         return None, variant
     return tuple(e["tile"]), e["variant"]
@@ -262,7 +262,8 @@ class Sim:
         p.rho_ref = rho_ref
         comp_name = compute if isinstance(compute, str) else {0: "auto", 1: "f32", 2: "f64"}[compute]
         if tile is None and tuned:
-            tile, variant = _tuned_shape(q, nx, ny, nz, storage, comp_name, variant)
+            tile, variant = _tuned_shape(q, nx, ny, nz, storage, comp_name, variant,
+                                         2 if two_component is not None else 1)
             if gravity is not None and any(gravity) and variant == 2:
                 variant = 3  # no pipelined gravity kernel: same tile, plain variant
         if tile is not None:
@@ -292,6 +293,8 @@ class Sim:
 
     @classmethod
     def from_spec(cls, spec, **kw):
+        if getattr(spec, "two_component", None) is not None:
+            kw.setdefault("two_component", spec.two_component)
         return cls(q=spec.q, nx=spec.nx, ny=spec.ny, nz=spec.nz, tau=spec.tau, G=spec.G,
                    rho_l=spec.rho_l, rho_g=spec.rho_g, amp=spec.amp, seed=spec.seed,
                    theta=spec.theta, K=spec.K, film_max=spec.film_max, **kw)

@@ -1,6 +1,6 @@
 """Runs the library's step-kernel autotuner (sc_autotune) on the standard workloads and stores
 the chosen tile shapes in tuned_shapes.json beside this file.  The binding applies a stored shape
-to every new simulation of the same lattice, box, storage and compute type.
+to every new simulation of the same lattice, box, storage, compute type and component count.
 
     python -m paper_1708_01608_amd.tune [--workloads foam_3d,foam_2d,...]
 """
@@ -13,8 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned_shapes.json")
 
 
-def key(q, nx, ny, nz, storage, compute):
-    return f"q{q}_{nx}x{ny}x{nz}_{storage}_{compute}"
+def key(q, nx, ny, nz, storage, compute, components=1):
+    k = f"q{q}_{nx}x{ny}x{nz}_{storage}_{compute}"
+    return k if components == 1 else k + f"_{components}c"
 
 
 def load():
@@ -30,7 +31,8 @@ def main():
     from paper_1708_01608_amd import workloads as W
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads", default="foam_3d,foam_2d,two_bubble,foam_3d_large")
+    ap.add_argument("--workloads",
+                    default="foam_3d,foam_2d,two_bubble,foam_3d_large,mixture_2d,mixture_3d")
     ap.add_argument("--trials", type=int, default=4)
     args = ap.parse_args()
     table = load()
@@ -40,6 +42,8 @@ def main():
         "two_bubble": (W.two_bubble, [("f32", "f64"), ("f32", "f32")]),
         "foam_3d_large": (W.foam_3d_large, [("f32", "f64"), ("f32", "f32"), ("f16", "f32"),
                                             ("bf16", "f32")]),
+        "mixture_2d": (W.mixture_2d, [("f32", "f64")]),
+        "mixture_3d": (W.mixture_3d, [("f32", "f64")]),
     }
     for name in args.workloads.split(","):
         make, combos = plan[name]
@@ -49,7 +53,8 @@ def main():
             s.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
             res = s.autotune(trials=args.trials)
             best = min(res, key=lambda e: e["us"])
-            k = key(spec.q, spec.nx, spec.ny, spec.nz, storage, compute)
+            k = key(spec.q, spec.nx, spec.ny, spec.nz, storage, compute,
+                    1 if spec.two_component is None else 2)
             table[k] = {"tile": list(best["tile"]), "variant": best["variant"],
                         "us_per_launch": round(best["us"], 2), "candidates": len(res)}
             print(json.dumps({k: table[k]}), flush=True)

@@ -14,6 +14,9 @@ Workloads (the paper publishes no dataset; these stand in for its experiments):
                   same generator and seed (nucleus count scaled by volume) is the error run.
   batch           4096 independent two-bubble D2Q9 boxes of uneven size, G, radius and gap (Sec. 4,
                   Fig. 3: merging as a function of bubble size).
+  mixture_2d      foam_2d's box and nuclei with a liquid and a gas component (Sec. 3: the agent's
+                  gas grows the bubbles; Sec. 3.1: two simulations side by side).
+  mixture_3d      foam_3d's box and nuclei with the two components.
 """
 from dataclasses import dataclass, field
 import math
@@ -64,6 +67,8 @@ class SimSpec:
     radii: np.ndarray = field(default_factory=lambda: np.zeros(0))
     budgets: np.ndarray = field(default_factory=lambda: np.zeros(0))
     rate: float = 0.0
+    # two components: (G_cross, tau_vapour, rho_vapour, rho_dissolved); None = one component
+    two_component: tuple = None
 
     @property
     def N(self):
@@ -152,6 +157,28 @@ def foam_3d_large(n=512, n_nuclei=400, seed=4, steps=2000, K=50):
 
 def foam_3d_error_run(seed=4, steps=2000):
     return foam_3d_large(n=128, n_nuclei=max(1, round(400 / 64)), seed=seed, steps=steps)
+
+
+# The mixture's parameters: cross repulsion G_cross, gas relaxation time (<= 0: the liquid's),
+# gas density in the nuclei and dissolved in the liquid; the liquid component is 1.0 in the
+# liquid and 0.05 in the nuclei.
+MIXTURE = (1.5, 1.0, 1.0, 0.05)
+
+
+def _mixture(spec, name):
+    spec.name = name
+    spec.G = 0.0
+    spec.rho_l, spec.rho_g = 1.0, 0.05
+    spec.two_component = MIXTURE
+    return spec
+
+
+def mixture_2d(n=1024, n_nuclei=64, seed=2, steps=20000, K=100):
+    return _mixture(foam_2d(n, n_nuclei, seed, steps, K), "mixture_2d")
+
+
+def mixture_3d(n=256, n_nuclei=200, seed=3, steps=5000, K=50):
+    return _mixture(foam_3d(n, n_nuclei, seed, steps, K), "mixture_3d")
 
 
 @dataclass

@@ -126,6 +126,8 @@ def test_gravity_parameters_are_checked(lib, g, storage, variant, code):
     ("components", 3, sc.SC_E_INVAL), ("rho_vapour", 0.0, sc.SC_E_INVAL),
     ("tau_vapour", 0.5, sc.SC_E_INVAL), ("storage", 1, sc.SC_E_UNSUPPORTED),
     ("compute", 1, sc.SC_E_UNSUPPORTED), ("barrier", 1, sc.SC_E_UNSUPPORTED),
+    ("rho_ref", 1.0, sc.SC_E_UNSUPPORTED), ("step_variant", 2, sc.SC_E_INVAL),
+    ("tile_x", 32, sc.SC_E_INVAL),
 ])
 def test_two_component_parameters_are_checked(lib, field, value, code):
     p = sc.Params()
@@ -174,3 +176,26 @@ def test_library_lattice_is_a_valid_velocity_set(lib, q):
     # opposite pairs sit next to each other
     for i in range(1, q, 2):
         assert np.array_equal(e[i], -e[i + 1])
+
+
+@pytest.mark.parametrize("q,tile,ok", [
+    (9, (64, 1, 8), True), (9, (512, 1, 3), True), (9, (32, 1, 8), False),
+    (19, (32, 4, 16), True), (19, (128, 4, 64), True), (19, (256, 4, 64), False),
+    (19, (16, 16, 16), False),
+])
+def test_two_component_tiles_are_checked(lib, q, tile, ok):
+    # the fused two-component kernel has its own shape set (both densities' rings in LDS)
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    p.components, p.lattice = 2, q
+    p.nx, p.ny, p.nz = 64, 64, (1 if q == 9 else 64)
+    p.tile_x, p.tile_y, p.tile_z = tile
+    h = C.c_void_p()
+    rc = lib.sc_create(C.byref(p), C.byref(h))
+    if ok:
+        # accepted by validation: on a host without a GPU creation fails at the device instead
+        assert rc in (sc.SC_OK, sc.SC_E_DEVICE, sc.SC_E_NOMEM)
+        if rc == sc.SC_OK:
+            lib.sc_destroy(h)
+    else:
+        assert rc == sc.SC_E_INVAL

@@ -58,6 +58,52 @@ def test_two_component_fields_match_oracle(case):
     assert np.array_equal(g.last_labels(), o.labels())
 
 
+@pytest.mark.parametrize("q,shape,tile,variant", [
+    (9, (150, 70, 1), (64, 1, 8), 3),      # 3 row tiles (the last 22 wide), 8 + 8 + ... + 6 rows
+    (9, (96, 40, 1), (512, 1, 3), 1),      # one tile wider than the box, chunks of 3 rows
+    (19, (40, 20, 18), (32, 4, 16), 3),    # 2 x-tiles (the last 8 wide), z chunks 16 + 2
+    (19, (36, 18, 20), (64, 8, 7), 1),     # one x-tile wider than the box, y 8 + 8 + 2, z 7 + 7 + 6
+    (19, (48, 20, 16), (128, 4, 64), 3),   # one z chunk covering the box
+])
+def test_fused_kernel_shapes_match_oracle(q, shape, tile, variant):
+    # a central bubble and one across the periodic corner, on tiles with ragged edges
+    nx, ny, nz = shape
+    R = 7.0 if q == 9 else 4.5
+    zc = 0.0 if q == 9 else nz / 2 - 0.5
+    centres = [(nx / 2 - 0.5, ny / 2 - 0.5, zc), (1.5, 2.5, 0.0 if q == 9 else 1.5)]
+    kw = dict(tau=0.9, G=0.0, rho_l=1.0, rho_g=0.05, amp=1e-3, seed=11, K=20)
+    tc = (1.5, 0.8, 1.0, 0.05)
+    o = OracleSim(q, nx, ny, nz, two_component=tc, **kw)
+    g = sc.Sim(q=q, nx=nx, ny=ny, nz=nz, tile=tile, variant=variant, two_component=tc, **kw)
+    assert g.step_config() == (*tile, variant)
+    for s in (o, g):
+        s.seed_nuclei(np.asarray(centres), np.full(2, R), np.zeros(2), 0.0)
+    _announce(f"fused mixture kernel q={q} box={shape} tile={tile} variant={variant}")
+    g.step(40)
+    o.step(40)
+    e_rho, e_u, e_v = _errors(g, o)
+    print(f"rho_l {e_rho:.3e} u {e_u:.3e} rho_v {e_v:.3e}")
+    assert e_rho <= RHO_TOL and e_u <= U_TOL and e_v <= RHO_TOL
+    assert np.array_equal(g.last_labels(), o.labels())
+
+
+def test_autotune_of_the_mixture_keeps_the_state():
+    o, g = _pair(19, (40, 24, 24), [(19.5, 11.5, 11.5)], [6.0], [0.0], 0.0, K=10)
+    rho0, _, _ = g.fields()
+    v0 = g.gas_density()
+    _announce("mixture autotune")
+    res = g.autotune(trials=1)
+    assert len(res) == 30  # 5 tiles x 3 plane counts x 2 store variants
+    rho1, _, _ = g.fields()
+    assert np.array_equal(rho0, rho1) and np.array_equal(v0, g.gas_density())
+    best = min(res, key=lambda e: e["us"])
+    assert g.step_config() == (*best["tile"], best["variant"])
+    g.step(30)
+    o.step(30)
+    e_rho, e_u, e_v = _errors(g, o)
+    assert e_rho <= RHO_TOL and e_u <= U_TOL and e_v <= RHO_TOL
+
+
 def test_fed_bubble_grows_on_gpu_as_in_oracle():
     o, g = _pair(9, (64, 64, 1), [(31.5, 31.5, 0)], [10.0], [1e9], 0.05)
     n0 = g.bubbles()[0]["n"]

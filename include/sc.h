@@ -115,7 +115,9 @@ typedef struct sc_params {
      * FP32 storage with rho_ref <= 0 (unshifted) and FP64 arithmetic only, no barrier, no
      * gravity (SC_E_UNSUPPORTED).  The step is one fused kernel for both components; its tiles
      * are D2Q9 tile_x in {64, 128, 256, 512}, D3Q19 (tile_x, tile_y) in {(32,4), (32,8), (64,4),
-     * (64,8), (128,4)}, any tile_z >= 1 planes, step_variant 1 or 3 (SC_E_INVAL otherwise). */
+     * (64,8), (128,4)}, any tile_z >= 1 planes, step_variant 1 or 3 (both components per
+     * thread; 3: non-temporal stores) or, in D3Q19, 4 or 5 (one component per wave, the node's
+     * two threads meeting in LDS; 5: non-temporal stores); SC_E_INVAL otherwise. */
     int32_t components;        /* 1 (default) or 2 */
     int32_t reserved2;
     double G_cross;            /* cross interaction, > 0 repels (default 1.5) */

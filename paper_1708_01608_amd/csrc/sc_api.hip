@@ -300,7 +300,7 @@ std::vector<StepShape> tune_candidates_2c(int q)
         const int tiles[][2] = {{32, 4}, {32, 8}, {64, 4}, {64, 8}, {128, 4}};
         for (auto& t : tiles)
             for (int tz : {16, 32, 64})
-                for (int v : {1, 3}) c.push_back(StepShape{t[0], t[1], tz, v});
+                for (int v : {1, 3, 4, 5}) c.push_back(StepShape{t[0], t[1], tz, v});
     }
     return c;
 }

@@ -48,7 +48,7 @@ hipError_t launch_step(int q, int storage, int compute, const void* src, void* d
 // Two-component step (FP32 unshifted storage, FP64 arithmetic): one fused marching kernel per
 // step (both densities over the tile and its ring in LDS, the cross forces, the common velocity,
 // both collisions with streaming).  Shapes: tile_x, tile_y, planes = tile_z, variant 1 or 3
-// (non-temporal stores).
+// (non-temporal stores); in D3Q19 also 4 or 5 (one component per wave; 5 non-temporal).
 struct Step2cArgs {
     int nx, ny, nz;
     int planes;  // set by launch_step2c from the shape

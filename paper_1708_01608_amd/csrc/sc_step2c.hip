@@ -254,6 +254,130 @@ __global__ void __launch_bounds__(TX* TY) k_mix3d(const float* __restrict__ sl,
 }
 
 // ------------------------------------------------------------------------------------------
+// D3Q19, one component per wave: threads [0, T) carry the liquid of the T = TX x TY tile nodes,
+// threads [T, 2T) the gas, so each thread holds one component's populations (the register
+// budget of the one-component kernel) and every wave reads and writes a single component
+// through scalar bases.  Besides the density rings, the momenta of both components go to LDS at
+// load time (three plane slots: plane z is read between the barriers of iterations z and z+1,
+// plane z+3 is written only after the second of them); the collision reads its partner's
+// density and momentum there.
+// ------------------------------------------------------------------------------------------
+template <int TX, int TY, bool NT>
+__global__ void __launch_bounds__(2 * TX* TY) k_mix3d_split(const float* __restrict__ sl,
+                                                            const float* __restrict__ sv,
+                                                            float* __restrict__ dl,
+                                                            float* __restrict__ dv, Step2cArgs a,
+                                                            StepGrid grid)
+{
+    using L = lat<19>;
+    constexpr int T = TX * TY;
+    __shared__ double rs[2][4][TY + 2][TX + 2];  // [component][plane slot][y][x] densities
+    __shared__ double js[2][3][3][T];            // [component][plane slot][axis][node] momenta
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t N = a.N;
+    const int lb = logical_block(grid);
+    const int bx = lb % grid.gx;
+    const int by = (lb / grid.gx) % grid.gy;
+    const int bz = lb / (grid.gx * grid.gy);
+    // component of this wave (T is a multiple of 64, so no wave straddles the two halves)
+    const int comp = __builtin_amdgcn_readfirstlane((int)threadIdx.x >= T ? 1 : 0);
+    const int oc = comp ^ 1;
+    const int t = (int)threadIdx.x - comp * T;
+    const float* __restrict__ src = comp ? sv : sl;
+    float* __restrict__ dst = comp ? dv : dl;
+    const double il = 1.0 / a.tau_l, iv = 1.0 / a.tau_v;
+    const double ia = comp ? iv : il;
+    const double ka = -(comp ? a.tau_v : a.tau_l) * a.Gx;  // tau_a F_a / rho_a = ka sum(rho_b)
+    const int tx = t % TX, ty = t / TX;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * a.planes;
+    const int wx = min(TX, nx - x0), wy = min(TY, ny - y0);
+    const int ze = min(z0 + a.planes, nz);
+    const bool own = tx < wx && ty < wy;
+    const int x = x0 + (own ? tx : 0), y = y0 + (own ? ty : 0);
+    const int xm = wrap_once(x - 1, nx), xp = wrap_once(x + 1, nx);
+    const int ym = wrap_once(y - 1, ny), yp = wrap_once(y + 1, ny);
+
+    // ring node of this thread for its component (the host checks 2 (TX + 2) + 2 TY <= T)
+    const int nring = 2 * (wx + 2) + 2 * wy;
+    const bool ring = t < nring;
+    int hlx, hly;
+    if (t < wx + 2) {
+        hlx = t; hly = 0;
+    } else if (t < 2 * (wx + 2)) {
+        hlx = t - (wx + 2); hly = wy + 1;
+    } else if (t < 2 * (wx + 2) + wy) {
+        hlx = 0; hly = 1 + t - 2 * (wx + 2);
+    } else {
+        hlx = wx + 1; hly = 1 + t - 2 * (wx + 2) - wy;
+    }
+    const int hx = wrap_once(x0 - 1 + (ring ? hlx : 1), nx);
+    const int hy = wrap_once(y0 - 1 + (ring ? hly : 1), ny);
+    const int hxm = wrap_once(hx - 1, nx), hxp = wrap_once(hx + 1, nx);
+    const int hym = wrap_once(hy - 1, ny), hyp = wrap_once(hy + 1, ny);
+
+    float cur[19], nxt[19];
+
+    // plane z: density into ring slot k, momentum into slot k3 (k3 < 0: not needed)
+    auto load_plane = [&](int z, int k, int k3, float* g) {
+        const int zm = wrap_once(z - 1, nz), zp = wrap_once(z + 1, nz);
+        if (own) {
+            pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z, zm, zp, g);
+            rs[comp][k][ty + 1][tx + 1] = sum_dev<19, double>(g);
+            if (k3 >= 0) {
+                double jx, jy, jz;
+                momentum<19>(g, jx, jy, jz);
+                js[comp][k3][0][t] = jx;
+                js[comp][k3][1][t] = jy;
+                js[comp][k3][2][t] = jz;
+            }
+        }
+        if (ring) {
+            float h[19];
+            pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z, zm, zp, h);
+            rs[comp][k][hly][hlx] = sum_dev<19, double>(h);
+        }
+    };
+    load_plane(wrap_once(z0 - 1, nz), 0, -1, nxt);
+    load_plane(z0, 1, 0, cur);
+
+    int s3 = 0;  // momentum slot of plane z
+    for (int z = z0; z < ze; ++z) {
+        const int s = (z - z0 + 1) & 3;
+        const int sn = (s + 1) & 3, sp = (s + 3) & 3;
+        const int n3 = s3 == 2 ? 0 : s3 + 1;
+        load_plane(wrap_once(z + 1, nz), sn, n3, nxt);
+        __syncthreads();
+        if (own) {
+            // both components in a fixed order (liquid first), so the two threads of a node
+            // form the same common velocity
+            const double ra = rs[comp][s][ty + 1][tx + 1], rb = rs[oc][s][ty + 1][tx + 1];
+            const double rl = comp ? rb : ra, rv = comp ? ra : rb;
+            double jl[3], jv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                jl[c] = js[0][s3][c][t];
+                jv[c] = js[1][s3][c][t];
+            }
+            const double iden = recip(fma(rl, il, rv * iv));
+            const double upx = fma(jl[0], il, jv[0] * iv) * iden;
+            const double upy = fma(jl[1], il, jv[1] * iv) * iden;
+            const double upz = fma(jl[2], il, jv[2] * iv) * iden;
+            auto slot = [&](int i) { return L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s); };
+            double sx, sy, sz;
+            interaction_sum<19, double>(
+                [&](int i) { return rs[oc][slot(i)][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]]; }, sx,
+                sy, sz);
+            relax_store<19, double, float, NT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, ra,
+                                               ra, fma(ka, sx, upx), fma(ka, sy, upy),
+                                               fma(ka, sz, upz), ia);
+        }
+#pragma unroll
+        for (int i = 0; i < 19; ++i) cur[i] = nxt[i];
+        s3 = n3;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Reported fields: both densities (FP64, one pass), then rho_l, rho_v and the barycentric
 // velocity u = (j_l + j_v + (F_l + F_v) / 2) / (rho_l + rho_v).  Grid-stride, test cadence only.
 // ------------------------------------------------------------------------------------------
@@ -336,10 +460,11 @@ dim3 grid_nodes(int64_t N)
 
 bool step2c_shape_supported(int q, const StepShape& s)
 {
-    if (s.tile_z < 1 || (s.variant != 1 && s.variant != 3)) return false;
+    if (s.tile_z < 1) return false;
     if (q == SC_D2Q9)
-        return s.tile_y == 1 &&
+        return (s.variant == 1 || s.variant == 3) && s.tile_y == 1 &&
                (s.tile_x == 64 || s.tile_x == 128 || s.tile_x == 256 || s.tile_x == 512);
+    if (s.variant < 1 || s.variant > 5 || s.variant == 2) return false;
     if (q == SC_D3Q19) {
         const int tx = s.tile_x, ty = s.tile_y;
         return (tx == 32 && (ty == 4 || ty == 8)) || (tx == 64 && (ty == 4 || ty == 8)) ||
@@ -366,7 +491,8 @@ hipError_t launch_step2c(int q, const float* src_l, const float* src_v, float* d
     const int nb = g.gx * g.gy * g.gz;
     g.remap = (nb % 8 == 0) ? 1 : 0;
     const dim3 grid(nb);
-    const bool nt = s.variant == 3;
+    const bool nt = s.variant == 3 || s.variant == 5;
+    const bool split = s.variant >= 4;
 #define SC_M2(TX)                                                                                \
     if (s.tile_x == TX) {                                                                        \
         if (nt)                                                                                  \
@@ -379,6 +505,15 @@ hipError_t launch_step2c(int q, const float* src_l, const float* src_v, float* d
     }
 #define SC_M3(TX, TY)                                                                            \
     if (s.tile_x == TX && s.tile_y == TY) {                                                      \
+        if (split) {                                                                             \
+            if (nt)                                                                              \
+                hipLaunchKernelGGL((k_mix3d_split<TX, TY, true>), grid, dim3(2 * TX * TY), 0,   \
+                                   st, src_l, src_v, dst_l, dst_v, a, g);                        \
+            else                                                                                 \
+                hipLaunchKernelGGL((k_mix3d_split<TX, TY, false>), grid, dim3(2 * TX * TY), 0,  \
+                                   st, src_l, src_v, dst_l, dst_v, a, g);                        \
+            return hipGetLastError();                                                            \
+        }                                                                                        \
         if (nt)                                                                                  \
             hipLaunchKernelGGL((k_mix3d<TX, TY, true>), grid, dim3(TX * TY), 0, st, src_l,       \
                                src_v, dst_l, dst_v, a, g);                                       \

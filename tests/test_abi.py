@@ -178,18 +178,21 @@ def test_library_lattice_is_a_valid_velocity_set(lib, q):
         assert np.array_equal(e[i], -e[i + 1])
 
 
-@pytest.mark.parametrize("q,tile,ok", [
-    (9, (64, 1, 8), True), (9, (512, 1, 3), True), (9, (32, 1, 8), False),
-    (19, (32, 4, 16), True), (19, (128, 4, 64), True), (19, (256, 4, 64), False),
-    (19, (16, 16, 16), False),
+@pytest.mark.parametrize("q,tile,variant,ok", [
+    (9, (64, 1, 8), 1, True), (9, (512, 1, 3), 3, True), (9, (32, 1, 8), 1, False),
+    (9, (64, 1, 8), 4, False), (19, (32, 4, 16), 1, True), (19, (128, 4, 64), 3, True),
+    (19, (64, 8, 16), 4, True), (19, (32, 4, 16), 5, True), (19, (32, 4, 16), 2, False),
+    (19, (32, 4, 16), 6, False), (19, (256, 4, 64), 1, False), (19, (16, 16, 16), 1, False),
 ])
-def test_two_component_tiles_are_checked(lib, q, tile, ok):
-    # the fused two-component kernel has its own shape set (both densities' rings in LDS)
+def test_two_component_tiles_are_checked(lib, q, tile, variant, ok):
+    # the fused two-component kernels have their own shape set (both densities' rings in LDS);
+    # variants 4 and 5 (one component per wave) exist in D3Q19 only
     p = sc.Params()
     lib.sc_params_init(C.byref(p))
     p.components, p.lattice = 2, q
     p.nx, p.ny, p.nz = 64, 64, (1 if q == 9 else 64)
     p.tile_x, p.tile_y, p.tile_z = tile
+    p.step_variant = variant
     h = C.c_void_p()
     rc = lib.sc_create(C.byref(p), C.byref(h))
     if ok:

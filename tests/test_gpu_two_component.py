@@ -64,6 +64,11 @@ def test_two_component_fields_match_oracle(case):
     (19, (40, 20, 18), (32, 4, 16), 3),    # 2 x-tiles (the last 8 wide), z chunks 16 + 2
     (19, (36, 18, 20), (64, 8, 7), 1),     # one x-tile wider than the box, y 8 + 8 + 2, z 7 + 7 + 6
     (19, (48, 20, 16), (128, 4, 64), 3),   # one z chunk covering the box
+    # one component per wave
+    (19, (40, 20, 18), (32, 4, 16), 4),
+    (19, (36, 18, 20), (64, 8, 7), 5),
+    (19, (70, 22, 9), (64, 4, 4), 5),      # x 64 + 6, y 4 x 5 + 2, z 4 + 4 + 1
+    (19, (48, 20, 16), (128, 4, 64), 4),
 ])
 def test_fused_kernel_shapes_match_oracle(q, shape, tile, variant):
     # a central bubble and one across the periodic corner, on tiles with ragged edges
@@ -93,7 +98,7 @@ def test_autotune_of_the_mixture_keeps_the_state():
     v0 = g.gas_density()
     _announce("mixture autotune")
     res = g.autotune(trials=1)
-    assert len(res) == 30  # 5 tiles x 3 plane counts x 2 store variants
+    assert len(res) == 60  # 5 tiles x 3 plane counts x 4 variants
     rho1, _, _ = g.fields()
     assert np.array_equal(rho0, rho1) and np.array_equal(v0, g.gas_density())
     best = min(res, key=lambda e: e["us"])

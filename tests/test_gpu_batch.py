@@ -5,25 +5,9 @@ import pytest
 from oracle import OracleSim
 from paper_1708_01608_amd import sc
 from paper_1708_01608_amd import workloads as W
+from batch_oracle import oracle_run, oracle_steps_parallel
 
 pytestmark = pytest.mark.gpu
-
-
-def oracle_run(s, max_steps):
-    """The oracle under the batch's stopping rule: test every K steps; stop at the first
-    criterion firing, the first shared component of the two nuclei, or max_steps."""
-    o = OracleSim(s.q, s.nx, s.ny, 1, s.tau, s.G, s.rho_l, s.rho_g, s.amp, s.seed, s.theta, s.K,
-                  s.film_max)
-    o.seed_nuclei(s.centres, s.radii, s.budgets, 0.0)
-    if o.topo_events():
-        return o, -1, 0, 0
-    while o.t < max_steps:
-        o.step(min(s.K, max_steps - o.t))
-        ev, te = o.events(), o.topo_events()
-        if ev or te:
-            break
-    ev, te = o.events(), o.topo_events()
-    return o, (ev[0]["step"] if ev else -1), (te[0]["step"] if te else -1), o.t
 
 
 def small_batch(n, seed=11, lo=64, hi=96, max_steps=300):
@@ -80,3 +64,28 @@ def test_batch_merge_steps_match_oracle_sample():
         if (g["merge_step"], g["topo_step"], g["steps_run"]) != (m, tp, t):
             mism.append(k)
     assert not mism, mism
+
+
+def test_full_batch_merge_steps_match_oracle_on_sampled_boxes():
+    """The batch workload at full size (4096 boxes of 64..256 per side, up to 5000 steps) in the
+    launch configuration the benchmark times (tuned node slots per lane, one persistent launch);
+    merge, topological and final steps of 64 evenly sampled boxes against the oracle."""
+    spec = W.batch()
+    print("[gpu] full batch: 4096 boxes, tune + one persistent launch", flush=True)
+    b = sc.Batch(spec)
+    rb, _ = b.tune(trial_steps=50)
+    res, ms = b.run()
+    b.close()
+    ks = list(range(0, spec.n, spec.n // 64))[:64]
+    print(f"gpu job {ms:.0f} ms with {rb} node slots per lane; oracle on {len(ks)} boxes",
+          flush=True)
+    ora = oracle_steps_parallel([spec.instance(k) for k in ks], spec.max_steps)
+    mism = []
+    for k, (m, tp, t) in zip(ks, ora):
+        g = res[k]
+        if (g["merge_step"], g["topo_step"], g["steps_run"]) != (m, tp, t):
+            mism.append((k, (g["merge_step"], g["topo_step"], g["steps_run"]), (m, tp, t)))
+    fired = sum(1 for m, _, _ in ora if m >= 0)
+    topo = sum(1 for m, tp, _ in ora if m < 0 and tp >= 0)
+    print(f"sample: {fired} criterion merges, {topo} topological first, mismatches {mism}")
+    assert not mism

@@ -84,7 +84,8 @@ typedef struct sc_params {
     const sc_allocator* allocator; /* NULL: hipMalloc / hipFree */
     int32_t tile_x, tile_y, tile_z; /* step-kernel tile; 0 selects the tuned default */
     int32_t step_variant;      /* 0 default, 1 plain marching, 2 software-pipelined (D3Q19),
-                                  3 plain with non-temporal population stores */
+                                  3 plain with non-temporal population stores; with two
+                                  components also 4 and 5 (D3Q19, one component per wave) */
     /* Modified Shan-Chen barrier (Sec. 3.1, Fig. 1 steps 3-6: each bubble on its own lattice,
      * meeting the others only through the liquid until the criterion flips eta_m).  barrier = 1:
      * every bubble owns its gas nodes and `corona` liquid layers around them (grown by lattice

@@ -338,6 +338,7 @@ def main():
             "avg_launch_us": round(avg_s * 1e6, 2),
             "launches": r["launches"],
         },
+        "stencil_only_MLUPS": round(spec.N / avg_s / 1e6, 1),
         "breakdown_ms": {
             "step_kernel": round(r["step_ms"], 3),
             "source": round(r["src_ms"], 3),

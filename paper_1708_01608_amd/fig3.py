@@ -1,13 +1,14 @@
 """Size sweep of the film at rupture (the experiment behind Fig. 3 and the fits of Sec. 4).
 
 For each bubble radius R_b, two equal bubbles with a `gap`-node liquid film on the x mid-line of
-a periodic D2Q9 box (the two-bubble geometry) are run on the GPU until the pressure-Laplacian
-criterion fires; at that test pass the film geometry gives the critical thickness h_c and the
+a periodic D2Q9 box (the two-bubble geometry; with --lattice 19, two spheres in a D3Q19 box) are
+run on the GPU until the pressure-Laplacian criterion fires; at that test pass the film geometry gives the critical thickness h_c and the
 disc radius R_d.  The paper fits h_c = 0.002 R_d^2 - 0.003 R_d + 0.035 and
 R_d = 2.088 ln R_b + 0.114 in its own (unstated) units; here the same two fits are made in lattice
 units, so only the trends compare.
 
     python -m paper_1708_01608_amd.fig3 [--radii 8,10,...] [--gap 4] [--max-steps 20000]
+                                        [--lattice 9|19] [--barrier]
 """
 import argparse
 import json
@@ -17,7 +18,7 @@ import sys
 import numpy as np
 
 
-def run(radii, gap, max_steps, barrier=False, K=10):
+def run(radii, gap, max_steps, barrier=False, K=10, lattice=9):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from paper_1708_01608_amd import sc
     from paper_1708_01608_amd import workloads as W
@@ -26,10 +27,16 @@ def run(radii, gap, max_steps, barrier=False, K=10):
     for R in radii:
         nx = int(4 * R + gap + 32)
         ny = int(2 * R + 32)
-        spec = W.two_bubble(nx=nx + nx % 2, ny=ny + ny % 2, radius=float(R), gap=gap, K=K)
+        nx, ny = nx + nx % 2, ny + ny % 2
+        if lattice == 9:
+            spec = W.two_bubble(nx=nx, ny=ny, radius=float(R), gap=gap, K=K)
+            box = [nx, ny]
+        else:
+            spec = W.two_bubble_3d(nx=nx, ny=ny, nz=ny, radius=float(R), gap=gap, K=K)
+            box = [nx, ny, ny]
         s = sc.Sim.from_spec(spec, barrier=barrier)
         s.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
-        row = {"R_b": R, "box": [spec.nx, spec.ny], "gap": gap, "fired": False}
+        row = {"R_b": R, "box": box, "gap": gap, "fired": False}
         while s.t < max_steps:
             s.step(K)
             ev = s.merge_events()
@@ -72,9 +79,11 @@ def main():
     ap.add_argument("--gap", type=int, default=4)
     ap.add_argument("--max-steps", type=int, default=20000)
     ap.add_argument("--barrier", action="store_true")
+    ap.add_argument("--lattice", type=int, default=9, choices=(9, 19),
+                    help="9: discs in a D2Q9 box; 19: spheres in a D3Q19 box")
     args = ap.parse_args()
     radii = [int(v) for v in args.radii.split(",")]
-    rows = run(radii, args.gap, args.max_steps, args.barrier)
+    rows = run(radii, args.gap, args.max_steps, args.barrier, lattice=args.lattice)
     print(json.dumps({"fits": fits(rows)}), flush=True)
 
 

@@ -7,6 +7,7 @@ by each side itself from (seed, node index) with SplitMix64.
 Workloads (the paper publishes no dataset; these stand in for its experiments):
   two_bubble      two bubbles of radius 15, gap 4, on a 128^2 D2Q9 box (Sec. 4, Fig. 2: two bubbles
                   approaching without gravity).
+  two_bubble_3d   the same pair as two spheres in a D3Q19 box (film-size sweep in 3D).
   foam_2d         1024^2 D2Q9 with 64 random nuclei of radius 3 (Sec. 3.1: time-random nucleation
                   sites, blowing agent decomposed at them; Sec. 4, Fig. 4: foam structure).
   foam_3d         256^3 D3Q19 with 200 random nuclei (the 3D version of foam_2d).
@@ -84,6 +85,16 @@ def two_bubble(amp=1e-3, seed=1, nx=128, ny=128, radius=15.0, gap=4, K=10, steps
     centres = pair_centres(nx, ny, radius, gap)
     return SimSpec(name="two_bubble", q=9, nx=nx, ny=ny, tau=1.0, G=-5.0, rho_l=1.93, rho_g=0.16,
                    amp=amp, seed=seed, K=K, steps=steps, centres=centres,
+                   radii=np.array([radius, radius]), budgets=np.zeros(2), rate=0.0)
+
+
+def two_bubble_3d(nx=96, ny=64, nz=64, radius=15.0, gap=4, K=10, steps=2000, amp=1e-3, seed=1):
+    """Two spheres on the x axis of a D3Q19 box, `gap` liquid nodes apart on the four node rows
+    nearest the axis (the 3D form of two_bubble, for the film-size sweep)."""
+    c = pair_centres(nx, ny, radius, gap)
+    c[:, 2] = nz / 2.0 - 0.5
+    return SimSpec(name="two_bubble_3d", q=19, nx=nx, ny=ny, nz=nz, tau=1.0, G=-5.0, rho_l=1.93,
+                   rho_g=0.16, amp=amp, seed=seed, K=K, steps=steps, centres=c,
                    radii=np.array([radius, radius]), budgets=np.zeros(2), rate=0.0)
 
 

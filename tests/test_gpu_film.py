@@ -83,3 +83,26 @@ def test_fig3_sweep_point_matches_oracle():
     h, rd, nl = o.film_geometry(0, 1)
     print(f"sweep R_b 12: gpu {row}; oracle h {h:.6f} R_d {rd} n {nl}")
     assert nl == row["n_lines"] and abs(h - row["h_c"]) <= 1e-4 * h
+
+
+@pytest.mark.parametrize("R,gap", [(8, 3), (12, 3)])
+def test_fig3_sweep_point_3d_matches_oracle(R, gap):
+    # the sweep's 3D form (two spheres, D3Q19): firing step, film node and geometry
+    from paper_1708_01608_amd import fig3
+
+    print(f"[gpu] 3D sweep point R_b {R} gap {gap}", flush=True)
+    row = fig3.run([R], gap, 400, lattice=19)[0]
+    assert row["fired"]
+    nx, ny, _ = row["box"]
+    spec = W.two_bubble_3d(nx=nx, ny=ny, nz=ny, radius=float(R), gap=gap)
+    o = oracle_from_spec(spec)
+    while o.t < row["step"]:
+        o.step(spec.K)
+        assert not o.events() or o.t == row["step"]
+    ev = o.events()
+    assert len(ev) == 1 and ev[0]["step"] == row["step"]
+    assert ev[0]["film_len"] == row["film_len"]
+    assert ev[0]["lap_p"] == pytest.approx(row["lap_p"], rel=1e-3)
+    h, rd, nl = o.film_geometry(0, 1)
+    print(f"3D sweep R_b {R}: gpu {row}; oracle h {h:.6f} R_d {rd} n {nl}")
+    assert nl == row["n_lines"] and abs(h - row["h_c"]) <= 1e-4 * h

@@ -470,6 +470,36 @@ def test_two_bubble_paint_and_statistics():
     assert np.all(row[62:66] == 0) and row[61] != 0 and row[66] != 0  # the 4-node film
 
 
+@pytest.mark.parametrize("R,gap", [(8, 3), (12, 4)])
+def test_two_bubble_3d_film_is_gap_nodes_on_the_axis_rows(R, gap):
+    # the spheres of the 3D sweep leave exactly `gap` liquid nodes on the four node rows nearest
+    # the axis, and wider films elsewhere (brute force over the painted labels)
+    nx = 4 * R + gap + 32
+    ny = 2 * R + 32
+    nx, ny = nx + nx % 2, ny + ny % 2
+    spec = W.two_bubble_3d(nx=nx, ny=ny, nz=ny, radius=float(R), gap=gap)
+    o = OracleSim(19, nx, ny, ny, spec.tau, spec.G, spec.rho_l, spec.rho_g, spec.amp, spec.seed,
+                  0.0, spec.K, 8)
+    o.seed_nuclei(spec.centres, spec.radii, spec.budgets, 0.0)
+    lab = o.labels().reshape(ny, ny, nx)
+    assert len(o.bubbles()) == 2
+    c = ny // 2
+    for z in (c - 1, c):
+        for y in (c - 1, c):
+            row = lab[z, y]
+            gasx = np.nonzero(row)[0]
+            inner = gasx[(gasx > nx // 2 - gap - 2) & (gasx < nx // 2 + gap + 2)]
+            left = inner[inner < nx // 2].max()
+            right = inner[inner > nx // 2 - 1].min()
+            assert right - left - 1 == gap
+    # one row further out the film is at least as wide
+    row = lab[c + 1, c]
+    gasx = np.nonzero(row)[0]
+    l = gasx[gasx < nx // 2].max()
+    r = gasx[gasx >= nx // 2].min()
+    assert r - l - 1 >= gap
+
+
 # ------------------------------------------------------------------------------------------
 # P12: mirror symmetry of the noiseless two-bubble box.
 # ------------------------------------------------------------------------------------------

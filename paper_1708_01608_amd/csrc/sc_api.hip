@@ -2,7 +2,8 @@
 //
 // Host side: parameter validation, device buffers, the time-step loop, and the bubble registry
 // (nuclei, FP64 agent budgets, merge and topological events).  All per-node work runs in the
-// HIP kernels of sc_step.hip and sc_test.hip; the host touches only per-bubble tables.
+// HIP kernels of sc_step.hip, sc_step2c.hip and sc_test.hip; the host touches only per-bubble
+// tables.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -74,7 +75,7 @@ struct sc_sim {
     double rho0 = 0.0;
 
     // two-component mode: the gas component's populations (same layout and cur as f) and the
-    // FP64 densities of both components that its step reads
+    // FP64 densities of both components that the reported fields are formed from
     bool two = false;
     void* fv[2] = {nullptr, nullptr};
     DevBuf dens2;

@@ -59,22 +59,18 @@ __device__ __forceinline__ int wrapi(int a, int n)
     return r < 0 ? r + n : r;
 }
 
-// ---- block reductions (fixed tree order: deterministic) --------------------------------------
+// ---- workgroup reductions (fixed order: deterministic) ----------------------------------------
+// A butterfly within each wave (the value of lane 0, whose association order is fixed), then the
+// waves in order.  All values of a test pass are reduced together behind one barrier.
 template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* red)
+__device__ __forceinline__ T wave_sum(T v)
 {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
 #pragma unroll
-    for (int s = kBatchThreads / 2; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    const T r = red[0];
-    __syncthreads();
-    return r;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
+
+constexpr int kWaves = kBatchThreads / 64;
 
 // ---- fill and paint (every node liquid plus noise, two balls of gas) -------------------------
 __device__ void batch_init(float* f, const BatchInst& in)
@@ -205,6 +201,12 @@ __device__ uint32_t batch_find(const uint32_t* par, uint32_t x)
     return x;
 }
 
+// Label of node n once the unions are done: its root, or kNone for a liquid node.
+__device__ __forceinline__ uint32_t batch_root(const uint32_t* par, uint32_t n)
+{
+    return par[n] == kNone ? kNone : batch_find(par, n);
+}
+
 __device__ void batch_unite(uint32_t* par, uint32_t a, uint32_t b)
 {
     while (true) {
@@ -238,8 +240,8 @@ __device__ __forceinline__ int min_img_i(int d, int n)
 }
 
 struct Scratch {
-    double d[kBatchThreads];
-    long long i[kBatchThreads];
+    long long i[kWaves][6];  // per wave: count, x and y offset sums of both bubbles
+    double d[kWaves][3];     // per wave: M, Jx, Jy
     int flag;
 };
 
@@ -252,28 +254,72 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
     using L = lat<9>;
     const int nx = in.nx, ny = in.ny, N = nx * ny;
     const int t = threadIdx.x;
-    for (int n = t; n < N; n += kBatchThreads) {
-        const double r = rho64(f, N, nx, ny, n % nx, n / nx);
-        par[n] = r < in.theta ? (uint32_t)n : kNone;
-    }
-    __syncthreads();
-    for (int n = t; n < N; n += kBatchThreads) {
-        if (ld_par(par, n) == kNone) continue;
-        const int x = n % nx, y = n / nx;
+    // One sweep over the populations: the FP64 density of each node (in the oracle's order) for
+    // the mask, and the box totals from the same pulled values (on a periodic box the pulled
+    // populations of all nodes are all the populations).  The sweeps take U nodes per thread and
+    // iteration, loads first: a workgroup carries one box, so without that each iteration would
+    // wait out a full memory latency.
+    double M = 0.0, Jx = 0.0, Jy = 0.0;
+    constexpr int U1 = 2;
+    for (int n0 = t; n0 < N; n0 += U1 * kBatchThreads) {
+        float g[U1][9];
 #pragma unroll
-        for (int h = 0; h < L::nhalf; ++h) {
-            const int i = L::half[h];
-            const int m = wrap_once(x + L::ex[i], nx) + nx * wrap_once(y + L::ey[i], ny);
-            if (ld_par(par, m) == kNone) continue;
-            batch_unite(par, (uint32_t)n, (uint32_t)m);
+        for (int u = 0; u < U1; ++u) {
+            const int n = n0 + u * kBatchThreads;
+            if (n < N) {
+                const int x = n % nx, y = n / nx;
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    g[u][i] = f[(int64_t)i * N + wrap_once(x - L::ex[i], nx) +
+                                nx * wrap_once(y - L::ey[i], ny)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U1; ++u) {
+            const int n = n0 + u * kBatchThreads;
+            if (n < N) {
+                double r = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const double v = (double)g[u][i];
+                    r += v;
+                    if (L::ex[i] > 0) jx += v; else if (L::ex[i] < 0) jx -= v;
+                    if (L::ey[i] > 0) jy += v; else if (L::ey[i] < 0) jy -= v;
+                }
+                par[n] = r < in.theta ? (uint32_t)n : kNone;
+                M += r;
+                Jx += jx;
+                Jy += jy;
+            }
         }
     }
     __syncthreads();
-    for (int n = t; n < N; n += kBatchThreads) {
-        const uint32_t p = ld_par(par, n);
-        if (p != kNone) par[n] = batch_find(par, (uint32_t)n);
+    constexpr int U2 = 8;
+    for (int n0 = t; n0 < N; n0 += U2 * kBatchThreads) {
+        // gas or liquid never changes in this pass: one mask bit per gas node of the group
+        unsigned gas = 0;
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+            const int n = n0 + u * kBatchThreads;
+            if (n < N && ld_par(par, n) != kNone) gas |= 1u << u;
+        }
+        while (gas) {
+            const int u = __builtin_ctz(gas);
+            gas &= gas - 1;
+            const int n = n0 + u * kBatchThreads;
+            const int x = n % nx, y = n / nx;
+#pragma unroll
+            for (int h = 0; h < L::nhalf; ++h) {
+                const int i = L::half[h];
+                const int m = wrap_once(x + L::ex[i], nx) + nx * wrap_once(y + L::ey[i], ny);
+                if (ld_par(par, m) == kNone) continue;
+                batch_unite(par, (uint32_t)n, (uint32_t)m);
+            }
+        }
     }
     __syncthreads();
+    // the trees are left unflattened (par is read-only from here on): a gas node's label is the
+    // root its find returns
 
     // nucleus nodes and their components (root index, kNone if liquid)
     int nd[2];
@@ -282,11 +328,10 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
         const int x = wrapi((int)floor(in.cx[b] + 0.5), nx);
         const int y = wrapi((int)floor(in.cy[b] + 0.5), ny);
         nd[b] = x + nx * y;
-        comp[b] = par[nd[b]];
+        comp[b] = batch_root(par, (uint32_t)nd[b]);
     }
-    // statistics: counts and integer minimal-image offset sums from each bubble's anchor node,
-    // and the FP64 totals of the box
-    // the bubble of nucleus 1 is anchored at nucleus 0 when both share it
+    // statistics: counts and integer minimal-image offset sums from each bubble's anchor node
+    // (the bubble of nucleus 1 is anchored at nucleus 0 when both share it)
     int ax[2], ay[2];
     for (int b = 0; b < 2; ++b) {
         const int a = (b == 1 && comp[1] == comp[0]) ? nd[0] : nd[b];
@@ -294,32 +339,60 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
         ay[b] = a / nx;
     }
     long long cnt[2] = {0, 0}, sx[2] = {0, 0}, sy[2] = {0, 0};
-    double M = 0.0, Jx = 0.0, Jy = 0.0;
-    for (int n = t; n < N; n += kBatchThreads) {
-        const uint32_t p = par[n];
-        const int y = n / nx, x = n - y * nx;
-        for (int b = 0; b < 2; ++b) {
-            if (p == kNone || p != comp[b]) continue;
-            cnt[b] += 1;
-            sx[b] += min_img_i(x - ax[b], nx);
-            sy[b] += min_img_i(y - ay[b], ny);
-        }
+    constexpr int U3 = 8;
+    for (int n0 = t; n0 < N; n0 += U3 * kBatchThreads) {
+        unsigned gas = 0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const double g = (double)f[(int64_t)i * N + n];
-            M += g;
-            Jx += g * L::ex[i];
-            Jy += g * L::ey[i];
+        for (int u = 0; u < U3; ++u) {
+            const int n = n0 + u * kBatchThreads;
+            if (n < N && par[n] != kNone) gas |= 1u << u;
+        }
+        while (gas) {
+            const int u = __builtin_ctz(gas);
+            gas &= gas - 1;
+            const int n = n0 + u * kBatchThreads;
+            const uint32_t p = batch_find(par, (uint32_t)n);
+            const int y = n / nx, x = n - y * nx;
+            for (int b = 0; b < 2; ++b) {
+                if (p != comp[b]) continue;
+                cnt[b] += 1;
+                sx[b] += min_img_i(x - ax[b], nx);
+                sy[b] += min_img_i(y - ay[b], ny);
+            }
         }
     }
+    {
+        const long long vi[6] = {cnt[0], sx[0], sy[0], cnt[1], sx[1], sy[1]};
+        const double vd[3] = {M, Jx, Jy};
+        long long ri[6];
+        double rd[3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ri[k] = wave_sum(vi[k]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rd[k] = wave_sum(vd[k]);
+        if ((t & 63) == 0) {
+            const int w = t >> 6;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sh.i[w][k] = ri[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sh.d[w][k] = rd[k];
+        }
+    }
+    __syncthreads();
+    // (sh is next written in the following test pass, behind further barriers)
     long long tot_i[6];
-    tot_i[0] = block_sum(cnt[0], sh.i);
-    tot_i[1] = block_sum(sx[0], sh.i);
-    tot_i[2] = block_sum(sy[0], sh.i);
-    tot_i[3] = block_sum(cnt[1], sh.i);
-    tot_i[4] = block_sum(sx[1], sh.i);
-    tot_i[5] = block_sum(sy[1], sh.i);
-    const double tM = block_sum(M, sh.d), tJx = block_sum(Jx, sh.d), tJy = block_sum(Jy, sh.d);
+    double tot_d[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        tot_i[k] = sh.i[0][k];
+        for (int w = 1; w < kWaves; ++w) tot_i[k] += sh.i[w][k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        tot_d[k] = sh.d[0][k];
+        for (int w = 1; w < kWaves; ++w) tot_d[k] += sh.d[w][k];
+    }
+    const double tM = tot_d[0], tJx = tot_d[1], tJy = tot_d[2];
 
     if (t == 0) {
         bool stop = false;
@@ -362,8 +435,8 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
                         if (node == prev) continue;
                         prev = node;
                         ++pos;
-                        if (pass == 0 && par[node] == comp[A]) sa = pos;
-                        if (pass == 1 && pos > sa && sb < 0 && par[node] == comp[B]) sb = pos;
+                        if (pass == 0 && batch_root(par, (uint32_t)node) == comp[A]) sa = pos;
+                        if (pass == 1 && pos > sa && sb < 0 && batch_root(par, (uint32_t)node) == comp[B]) sb = pos;
                     }
                     if (sa < 0) break;
                 }

@@ -191,18 +191,23 @@ __device__ __forceinline__ uint32_t ld_par(const uint32_t* p, int i)
     return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ uint32_t batch_find(const uint32_t* par, uint32_t x)
+// Root of x with path halving: each visited node is relinked to its grandparent.  Links only
+// ever point to smaller indices and a relinked node keeps an ancestor, so concurrent unions
+// (atomicMin on roots) and finds stay correct; chains get short after a few finds.
+__device__ uint32_t batch_find(uint32_t* par, uint32_t x)
 {
-    uint32_t p = ld_par(par, x);
-    while (p != x) {
-        x = p;
-        p = ld_par(par, x);
+    while (true) {
+        const uint32_t p = ld_par(par, x);
+        if (p == x) return x;
+        const uint32_t gp = ld_par(par, p);
+        if (gp == p) return p;
+        __hip_atomic_store(par + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = gp;
     }
-    return x;
 }
 
 // Label of node n once the unions are done: its root, or kNone for a liquid node.
-__device__ __forceinline__ uint32_t batch_root(const uint32_t* par, uint32_t n)
+__device__ __forceinline__ uint32_t batch_root(uint32_t* par, uint32_t n)
 {
     return par[n] == kNone ? kNone : batch_find(par, n);
 }
@@ -490,8 +495,11 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
     return stop;
 }
 
+// Waves per SIMD the compiler must fit (the second launch bound): one box per workgroup leaves
+// latency to hide, so with one node slot per lane the registers are capped for three waves (a
+// few spills, measured 16% faster than two); more slots need two.
 template <typename A, int RB>
-__global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs b)
+__global__ void __launch_bounds__(kBatchThreads, RB == 1 ? 3 : 2) k_batch(BatchArgs b)
 {
     __shared__ A ps[4 * RB * kBatchThreads];
     __shared__ Scratch sh;

@@ -346,7 +346,8 @@ def main():
             "wall": round(r["wall"] * 1e3, 3),
         },
     }
-    copy_gbs, read_gbs = sc.hbm_probe(min(bytes_per_launch // 2, 2550136832), 5)
+    # the copy ceiling on a buffer of the launch's size, at least 256 MiB so that it is HBM's
+    copy_gbs, read_gbs = sc.hbm_probe(max(min(bytes_per_launch // 2, 2550136832), 1 << 28), 5)
     out["roofline"]["measured_copy_GBps"] = round(copy_gbs, 1)
     out["roofline"]["measured_read_GBps"] = round(read_gbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)

@@ -21,6 +21,12 @@
  * Everything the paper leaves open (lattice, forcing scheme, force sign and weights, noise,
  * labelling connectivity, film walk, ...) follows one stated reading per point; the readings
  * are listed with the design notes of the repository.
+ *
+ * Pins: every function below is checked by the test suite against something other than
+ * itself (closed forms, conservation laws, brute force, the coexistence and Laplace laws, the
+ * spinodal sign rule of the criterion).  Parity unpinned: the merge and topological steps that
+ * a run produces (and, with the barrier, whether a film holds), because the paper prints no
+ * merge time or film profile to compare with; they are compared only GPU against oracle.
  */
 #ifndef SC_ORACLE_H
 #define SC_ORACLE_H

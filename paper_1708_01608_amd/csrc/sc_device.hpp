@@ -88,6 +88,15 @@ __device__ __forceinline__ float weight<19, float>(int i) { return lat<19>::wf[i
 template <>
 __device__ __forceinline__ double weight<19, double>(int i) { return lat<19>::wd[i]; }
 
+// The FP32 weight's rounding error w - (float)w: with it, w x takes two FMAs to the accuracy of
+// an FP64 weight.  1/9, 1/18 and 1/36 are not binary fractions; their FP32 rounding (relative
+// ~3e-8) would otherwise bias every node's equilibrium by the same amount at every step.
+template <int Q>
+__device__ __forceinline__ float weight_lo(int i)
+{
+    return (float)(lat<Q>::wd[i] - (double)lat<Q>::wf[i]);
+}
+
 // p(rho) = rho/3 + (G/6) psi^2 in FP64 (Sec. 3.1 EOS; 0.166 read as G cs^2 / 2).
 __device__ __forceinline__ double pressure_d(double rho, double G)
 {

@@ -3,6 +3,8 @@
 // the grouped interaction sum and the forced BGK collision.
 #pragma once
 
+#include <type_traits>
+
 #include "sc_device.hpp"
 #include "sc_internal.hpp"
 
@@ -163,7 +165,8 @@ __device__ __forceinline__ A e_dot(int i, A ux, A uy, A uz)
 
 // BGK relaxation towards f^eq(rho, u_eq) and the store of node `lane`:
 // g_i* = g_i + omega (f_i^eq - f_i), written as deviations (the stored shift cancels in the
-// difference: f_i - f_i^eq = g_i - (w_i drho + w_i rho P_i)).  Population i goes to byte offset
+// difference: f_i - f_i^eq = g_i - (w_i drho + w_i rho P_i)).  In FP32 the w_i drho term takes
+// the weight as a pair of floats.  Population i goes to byte offset
 // lane sizeof(S) from the direction's base dst + i N (below 2^32, as for the loads).
 template <int Q, typename A, typename S, bool NT = false>
 __device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint32_t lane,
@@ -179,7 +182,8 @@ __device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint
         const A P = fmad(eu, fmad((A)4.5, eu, (A)3), -usq15);
         const A w = weight<Q, A>(i);
         const A gi = (A)g[i];
-        const A h = fmad(-w, drho, gi);
+        A h = fmad(-w, drho, gi);
+        if constexpr (std::is_same<A, float>::value) h = fmad(-weight_lo<Q>(i), drho, h);
         const A d = fmad(w * rho, P, -h);
         const A gs = fmad(omega, d, gi);
         char* base = reinterpret_cast<char*>(dst + (int64_t)i * N);

@@ -98,7 +98,9 @@ class BatchResult(C.Structure):
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
     "sc_seed_nuclei", "sc_step", "sc_fields", "sc_laplacian_p", "sc_label_bubbles",
-    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei", "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density", "sc_set_gas_equilibrium", "sc_time",
+    "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei",
+    "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density",
+    "sc_set_gas_equilibrium", "sc_time",
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",

@@ -8,7 +8,7 @@ R_d = 2.088 ln R_b + 0.114 in its own (unstated) units; here the same two fits a
 units, so only the trends compare.
 
     python -m paper_1708_01608_amd.fig3 [--radii 8,10,...] [--gap 4] [--max-steps 20000]
-                                        [--lattice 9|19] [--barrier]
+                                        [--lattice 9|19] [--barrier] [--mixture --rate Q]
 """
 import argparse
 import json
@@ -18,7 +18,7 @@ import sys
 import numpy as np
 
 
-def run(radii, gap, max_steps, barrier=False, K=10, lattice=9):
+def run(radii, gap, max_steps, barrier=False, K=10, lattice=9, mixture=False, rate=0.0):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from paper_1708_01608_amd import sc
     from paper_1708_01608_amd import workloads as W
@@ -28,7 +28,10 @@ def run(radii, gap, max_steps, barrier=False, K=10, lattice=9):
         nx = int(4 * R + gap + 32)
         ny = int(2 * R + 32)
         nx, ny = nx + nx % 2, ny + ny % 2
-        if lattice == 9:
+        if mixture:
+            spec = W.two_bubble_mixture(nx=nx, ny=ny, radius=float(R), gap=gap, K=K, rate=rate)
+            box = [nx, ny]
+        elif lattice == 9:
             spec = W.two_bubble(nx=nx, ny=ny, radius=float(R), gap=gap, K=K)
             box = [nx, ny]
         else:
@@ -81,9 +84,14 @@ def main():
     ap.add_argument("--barrier", action="store_true")
     ap.add_argument("--lattice", type=int, default=9, choices=(9, 19),
                     help="9: discs in a D2Q9 box; 19: spheres in a D3Q19 box")
+    ap.add_argument("--mixture", action="store_true",
+                    help="two components (D2Q9): a liquid and a gas component")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="with --mixture: gas mass the agent adds to each bubble per step")
     args = ap.parse_args()
     radii = [int(v) for v in args.radii.split(",")]
-    rows = run(radii, args.gap, args.max_steps, args.barrier, lattice=args.lattice)
+    rows = run(radii, args.gap, args.max_steps, args.barrier, lattice=args.lattice,
+               mixture=args.mixture, rate=args.rate)
     print(json.dumps({"fits": fits(rows)}), flush=True)
 
 

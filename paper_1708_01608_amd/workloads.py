@@ -8,6 +8,8 @@ Workloads (the paper publishes no dataset; these stand in for its experiments):
   two_bubble      two bubbles of radius 15, gap 4, on a 128^2 D2Q9 box (Sec. 4, Fig. 2: two bubbles
                   approaching without gravity).
   two_bubble_3d   the same pair as two spheres in a D3Q19 box (film-size sweep in 3D).
+  two_bubble_mixture  the pair with two components, optionally fed (film-size sweep of growing
+                  bubbles).
   foam_2d         1024^2 D2Q9 with 64 random nuclei of radius 3 (Sec. 3.1: time-random nucleation
                   sites, blowing agent decomposed at them; Sec. 4, Fig. 4: foam structure).
   foam_3d         256^3 D3Q19 with 200 random nuclei (the 3D version of foam_2d).
@@ -96,6 +98,17 @@ def two_bubble_3d(nx=96, ny=64, nz=64, radius=15.0, gap=4, K=10, steps=2000, amp
     return SimSpec(name="two_bubble_3d", q=19, nx=nx, ny=ny, nz=nz, tau=1.0, G=-5.0, rho_l=1.93,
                    rho_g=0.16, amp=amp, seed=seed, K=K, steps=steps, centres=c,
                    radii=np.array([radius, radius]), budgets=np.zeros(2), rate=0.0)
+
+
+def two_bubble_mixture(nx=128, ny=128, radius=15.0, gap=4, K=10, rate=0.0, steps=2000, amp=1e-3,
+                       seed=1):
+    """two_bubble with the liquid and gas components (MIXTURE); with rate > 0 the agent feeds
+    each bubble `rate` mass of gas per step (unbounded budgets)."""
+    centres = pair_centres(nx, ny, radius, gap)
+    return SimSpec(name="two_bubble_mixture", q=9, nx=nx, ny=ny, tau=1.0, G=0.0, rho_l=1.0,
+                   rho_g=0.05, amp=amp, seed=seed, K=K, steps=steps, centres=centres,
+                   radii=np.array([radius, radius]), budgets=np.full(2, 1e12), rate=rate,
+                   two_component=MIXTURE)
 
 
 def pair_centres(nx, ny, radius, gap):

@@ -148,6 +148,16 @@ __device__ __forceinline__ void put<true, float>(float* p, float v)
 {
     __builtin_nontemporal_store(v, p);
 }
+template <>
+__device__ __forceinline__ void put<true, _Float16>(_Float16* p, _Float16 v)
+{
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t*>(p));
+}
+template <>
+__device__ __forceinline__ void put<true, __bf16>(__bf16* p, __bf16 v)
+{
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t*>(p));
+}
 
 // e_i . u with the exactly-zero components left out (a product with 0 would have to be kept
 // under IEEE rules; dropping it changes no value).

@@ -158,3 +158,25 @@ def test_two_component_merge_events_match_oracle():
     print("oracle", crit, [(e.step,) for e in te[:nt]], "\ngpu", g.merge_events(), g.topo_events())
     assert events_key(g.merge_events()) == crit
     assert [e["step"] for e in g.topo_events()] == [e.step for e in te[:nt]]
+
+
+def test_mixture_3d_full_size_conservation():
+    # the 256^3 mixture workload at full size in the benchmark's launch configuration: the
+    # mixture's mass is initial + spent agent budgets and its momentum is unchanged (both exact in
+    # real arithmetic, at any size)
+    from paper_1708_01608_amd import workloads as W
+
+    spec = W.mixture_3d()
+    _announce("mixture_3d 256^3 40 steps conservation")
+    g = sc.Sim.from_spec(spec)
+    g.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
+    t0 = g.totals()
+    g.step(40)
+    t1 = g.totals()
+    _, rem = g.nuclei(len(spec.radii))
+    spent = float((spec.budgets - rem).sum())
+    dm = abs(t1[0] - (t0[0] + spent)) / t0[0]
+    dj = float(np.max(np.abs(t1[1:] - t0[1:]))) / t0[0]
+    print(f"mixture 256^3: mass {dm:.2e} momentum {dj:.2e} (spent {spent:.3e})")
+    assert spent > 0 and dm <= 1e-7 and dj <= 1e-7
+    g.close()

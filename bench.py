@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--tile", default=None, help="tx,ty,tz[,variant] of the step kernel")
     ap.add_argument("--barrier", action="store_true",
                     help="run the modified Shan-Chen barrier (owner field read by the step kernel)")
+    ap.add_argument("--gravity", default=None, metavar="GX,GY[,GZ]",
+                    help="body force (rho - rho0) g in the step (drainage), e.g. 0,0,-1e-5")
     ap.add_argument("--autotune", action="store_true",
                     help="run the step-kernel autotuner before timing (default: the shape "
                          "stored by paper_1708_01608_amd.tune, else the built-in default)")
@@ -124,8 +126,9 @@ def run_gpu(spec, args, storage, compute, steps, warmup, tile=None):
     variant = 0
     if tile is not None and len(tile) == 4:
         tile, variant = tile[:3], tile[3]
+    gravity = [float(v) for v in args.gravity.split(",")] if args.gravity else None
     sim = sc.Sim.from_spec(spec, storage=storage, compute=compute, tile=tile, variant=variant,
-                           barrier=args.barrier)
+                           barrier=args.barrier, gravity=gravity)
     sim.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
     if tile is None and args.autotune:
         sim.autotune(trials=3)
@@ -293,7 +296,8 @@ def main():
     bytes_per_launch = bpn * spec.N
     avg_s = r["step_ms"] / 1e3 / max(r["launches"], 1)
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = (None if args.barrier else
+    # the counters were taken on the plain kernels
+    traffic = (None if args.barrier or args.gravity else
                traffic_from_profile(args.workload, args.storage, r["compute"], r["tile"]))
     out = {
         "metric": "Shan-Chen MLUPS & % of HBM roofline",
@@ -322,6 +326,7 @@ def main():
             "lattice_steps_per_step": spec.K,
             "step_tile": list(r["tile"]),
             "barrier": bool(args.barrier),
+            "gravity": args.gravity,
             "components": comps,
             "shape_source": ("--tile" if args.tile else "autotune" if args.autotune
                              else "tuned_shapes.json or default"),

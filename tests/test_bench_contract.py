@@ -1,0 +1,60 @@
+"""bench.py's output contract: one JSON line with the metric, the roofline object and the CPU
+baseline; one GPU only; algorithmic bytes and the counter-summary lookup."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_algorithmic_bytes_per_node():
+    assert bench.bytes_per_node(9, "f32") == 72
+    assert bench.bytes_per_node(19, "f32") == 152
+    assert bench.bytes_per_node(19, "f16") == 76
+    assert bench.bytes_per_node(19, "f32", components=2) == 304
+
+
+def test_counter_summary_is_used_only_for_the_profiled_kernel_and_tile():
+    with open(os.path.join(ROOT, "profiles", "step_counters_foam_3d_f32_f64.json")) as fh:
+        d = json.load(fh)
+    tile = tuple(d["tile"])
+    if d["kernel_hash"] == bench.step_kernel_hash():
+        assert bench.traffic_from_profile("foam_3d", "f32", "f64", tile) == d["hbm_bytes_per_launch"]
+    other = (tile[0] // 2,) + tile[1:]
+    assert bench.traffic_from_profile("foam_3d", "f32", "f64", other) is None
+    assert bench.traffic_from_profile("foam_3d", "f16", "f32", tile) is None
+
+
+@pytest.mark.gpu
+def test_bench_prints_the_contract_line():
+    print("[gpu] bench.py --steps 1 --warmup 0 --cpu-sample-steps 1", flush=True)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1",
+                        "--warmup", "0", "--cpu-sample-steps", "1"],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config", "roofline",
+              "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 1 and d["value"] > 0
+    assert d["config"]["workload"] == "foam_3d"
+    ro = d["roofline"]
+    assert ro["bound"] == "hbm" and ro["unit"] == "GB/s" and ro["peak"] == 8000.0
+    assert abs(ro["frac"] - ro["achieved"] / ro["peak"]) < 1e-3
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]

@@ -284,8 +284,11 @@ def main():
         return
     spec = workload_spec(args.workload)
     comps = 1 if spec.two_component is None else 2
-    if comps == 2 and (args.barrier or args.storage != "f32" or args.compute == "f32"):
-        print(json.dumps({"error": "the mixture runs on FP32 storage, FP64 arithmetic, no barrier"}))
+    if comps == 2 and (args.barrier or args.gravity or
+                       (args.storage == "f32") == (args.compute == "f32") and
+                       args.compute != "auto"):
+        print(json.dumps({"error": "the mixture runs FP32 storage with FP64 arithmetic or 16-bit "
+                                   "storage with FP32 arithmetic, no barrier, no gravity"}))
         sys.exit(2)
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     r = run_gpu(spec, args, args.storage, args.compute, args.steps, args.warmup, tile)

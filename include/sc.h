@@ -113,8 +113,10 @@ typedef struct sc_params {
      * p = (rho_l + rho_v)/3 + (G_cross/3) rho_l rho_v; totals sum both components; sc_fields
      * reports the liquid density and the mixture's barycentric velocity
      * (j_l + j_v + (F_l + F_v)/2) / (rho_l + rho_v); population access concerns the liquid.
-     * FP32 storage with rho_ref <= 0 (unshifted) and FP64 arithmetic only, no barrier, no
-     * gravity (SC_E_UNSUPPORTED).  The step is one fused kernel for both components; its tiles
+     * FP32 storage runs FP64 arithmetic, FP16 / BF16 storage FP32 arithmetic (the other
+     * pairings: SC_E_UNSUPPORTED); when the liquid's populations are shifted (rho_ref != 0, the
+     * default with 16-bit storage) the gas component's are shifted by w_i rho_dissolved.  No
+     * barrier, no gravity (SC_E_UNSUPPORTED).  The step is one fused kernel for both components; its tiles
      * are D2Q9 tile_x in {64, 128, 256, 512}, D3Q19 (tile_x, tile_y) in {(32,4), (32,8), (64,4),
      * (64,8), (128,4)}, any tile_z >= 1 planes, step_variant 1 or 3 (both components per
      * thread; 3: non-temporal stores) or, in D3Q19, 4 or 5 (one component per wave, the node's

@@ -49,6 +49,7 @@ struct sc_sim {
     int q = 9, d = 2;
     int64_t N = 0;
     double theta = 0.0, rho_ref = 0.0;
+    double rho_ref_v = 0.0;  // storage shift of the gas component (0 when the liquid's is 0)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     size_t es = 4;
@@ -191,6 +192,7 @@ FieldArgs field_args(const sc_sim* s)
     a.rho0d = s->rho0;
     a.f2 = s->two ? s->fv[s->cur] : nullptr;
     a.Gx = s->p.G_cross;
+    a.rho_ref2 = s->rho_ref_v;
     return a;
 }
 
@@ -203,6 +205,8 @@ Step2cArgs step2c_args(const sc_sim* s)
     a.tau_l = s->p.tau;
     a.tau_v = s->tau_v;
     a.Gx = s->p.G_cross;
+    a.ref_l = s->rho_ref;
+    a.ref_v = s->rho_ref_v;
     return a;
 }
 
@@ -242,6 +246,15 @@ InitArgs init_args(const sc_sim* s, double rho)
     a.amp = s->p.noise_amp;
     a.rho_ref = s->rho_ref;
     a.seed = s->p.noise_seed;
+    return a;
+}
+
+// Arguments of the gas component's state kernels: its own storage shift.
+InitArgs init_args_gas(const sc_sim* s, double rho)
+{
+    InitArgs a = init_args(s, rho);
+    a.amp = 0.0;
+    a.rho_ref = s->rho_ref_v;
     return a;
 }
 
@@ -453,7 +466,10 @@ int totals_now(sc_sim* s, double out[4])
     HIPX(hipStreamSynchronize(s->stream));
     if (s->two) {  // the mixture's totals: both components
         double gas[4];
-        HIPX(launch_totals(s->q, s->p.storage, s->fv[s->cur], (double*)s->partials.p, out_d, fa,
+        FieldArgs fg = fa;
+        fg.rho_ref_d = s->rho_ref_v;
+        fg.rho_ref = (float)s->rho_ref_v;
+        HIPX(launch_totals(s->q, s->p.storage, s->fv[s->cur], (double*)s->partials.p, out_d, fg,
                            s->stream));
         HIPX(hipMemcpyAsync(gas, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         HIPX(hipStreamSynchronize(s->stream));
@@ -803,10 +819,10 @@ int validate(const sc_params* p)
             return fail(SC_E_INVAL, "rho_vapour and rho_dissolved must be > 0");
         if (p->tau_vapour > 0.0 && !(p->tau_vapour > 0.5))
             return fail(SC_E_INVAL, "tau_vapour must be > 0.5 (or <= 0 for tau)");
-        if (p->storage != SC_STORE_F32 || p->compute == SC_COMPUTE_F32)
-            return fail(SC_E_UNSUPPORTED, "two components run on FP32 storage, FP64 arithmetic");
-        if (p->rho_ref > 0.0)
-            return fail(SC_E_UNSUPPORTED, "two components store unshifted populations (rho_ref <= 0)");
+        if (p->storage == SC_STORE_F32 && p->compute == SC_COMPUTE_F32)
+            return fail(SC_E_UNSUPPORTED, "two components on FP32 storage run FP64 arithmetic");
+        if (p->storage != SC_STORE_F32 && p->compute == SC_COMPUTE_F64)
+            return fail(SC_E_UNSUPPORTED, "two components on 16-bit storage run FP32 arithmetic");
         if (p->barrier) return fail(SC_E_UNSUPPORTED, "no barrier with two components");
         if (p->gravity[0] != 0.0 || p->gravity[1] != 0.0 || p->gravity[2] != 0.0)
             return fail(SC_E_UNSUPPORTED, "no gravity with two components");
@@ -951,6 +967,8 @@ int sc_create(const sc_params* p, sc_sim** out)
     s->two = p->components == 2;
     if (s->two) {
         s->tau_v = p->tau_vapour > 0.0 ? p->tau_vapour : p->tau;
+        // shifted liquid storage shifts the gas component by its bulk (dissolved) density
+        s->rho_ref_v = s->rho_ref != 0.0 ? p->rho_dissolved : 0.0;
         s->fv[0] = dev_alloc(s, bytes);
         s->fv[1] = dev_alloc(s, bytes);
         if (!s->fv[0] || !s->fv[1] || ensure(s, s->dens2, sizeof(double) * 2 * (size_t)s->N) != SC_OK) {
@@ -961,9 +979,7 @@ int sc_create(const sc_params* p, sc_sim** out)
     }
     hipError_t e = launch_init(s->q, p->storage, s->f[0], init_args(s, p->rho_liquid), s->stream);
     if (e == hipSuccess && s->two) {  // the liquid holds rho_dissolved of the gas component
-        InitArgs ga = init_args(s, p->rho_dissolved);
-        ga.amp = 0.0;
-        e = launch_init(s->q, p->storage, s->fv[0], ga, s->stream);
+        e = launch_init(s->q, p->storage, s->fv[0], init_args_gas(s, p->rho_dissolved), s->stream);
     }
     if (e == hipSuccess && p->barrier)
         e = launch_owner_seed(nullptr, nullptr, nullptr, 0, (uint16_t*)s->owner.p, s->N, s->stream);
@@ -1025,8 +1041,7 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
         s->topo_parent[k] = k;
     }
     const InitArgs ia = init_args(s, s->p.rho_gas);
-    InitArgs va = init_args(s, s->p.rho_vapour);  // the bubbles are filled with the gas component
-    va.amp = 0.0;
+    const InitArgs va = init_args_gas(s, s->p.rho_vapour);  // bubbles hold the gas component
     for (int k = 0; k < n; ++k) {
         if (s->rad[k] < 0.0) continue;
         HIPX(launch_paint(s->q, s->p.storage, s->f[s->cur], ia, &s->cen[3 * k], s->rad[k],
@@ -1050,9 +1065,8 @@ int sc_step(sc_sim* s, int32_t nsteps)
         hipEvent_t pe;
         TRY(prof_begin(s, SC_KERNEL_STEP, &pe));
         if (s->two)
-            HIPX(launch_step2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
-                               (float*)s->f[s->cur ^ 1], (float*)s->fv[s->cur ^ 1],
-                               step2c_args(s), s->shape, s->stream));
+            HIPX(launch_step2c(s->q, s->p.storage, s->f[s->cur], s->fv[s->cur], s->f[s->cur ^ 1],
+                               s->fv[s->cur ^ 1], step2c_args(s), s->shape, s->stream));
         else
             HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a,
                              s->shape, s->stream));
@@ -1098,7 +1112,7 @@ int sc_fields(sc_sim* s, float* rho, float* u, double* totals)
     if ((rho || u) && s->two) {  // liquid density and the mixture's barycentric velocity
         if (rho) TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
         if (u) TRY(ensure(s, s->u_out, sizeof(float) * (size_t)s->N * s->d));
-        HIPX(launch_fields2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
+        HIPX(launch_fields2c(s->q, s->p.storage, s->f[s->cur], s->fv[s->cur],
                              (double*)s->dens2.p, rho ? (float*)s->rho_out.p : nullptr, nullptr,
                              u ? (float*)s->u_out.p : nullptr, step2c_args(s), s->stream));
         if (rho)
@@ -1282,7 +1296,7 @@ int sc_gas_density(sc_sim* s, float* rho_v)
         return SC_OK;
     }
     TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
-    HIPX(launch_fields2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
+    HIPX(launch_fields2c(s->q, s->p.storage, s->f[s->cur], s->fv[s->cur],
                          (double*)s->dens2.p, nullptr, (float*)s->rho_out.p, nullptr,
                          step2c_args(s), s->stream));
     HIPX(hipMemcpyAsync(rho_v, s->rho_out.p, sizeof(float) * (size_t)s->N, hipMemcpyDeviceToHost,
@@ -1302,7 +1316,7 @@ int sc_set_gas_equilibrium(sc_sim* s, const double* rho_v)
     double* rd = (double*)s->tmp64.p;
     HIPX(hipMemcpyAsync(rd, rho_v, sizeof(double) * (size_t)s->N, hipMemcpyHostToDevice,
                         s->stream));
-    HIPX(launch_set_eq(s->q, s->p.storage, s->fv[s->cur], init_args(s, 0.0), rd, nullptr,
+    HIPX(launch_set_eq(s->q, s->p.storage, s->fv[s->cur], init_args_gas(s, 0.0), rd, nullptr,
                        s->stream));
     HIPX(hipStreamSynchronize(s->stream));
     return SC_OK;
@@ -1463,9 +1477,8 @@ int sc_autotune(sc_sim* s, int32_t trials, sc_tune_entry* out, int32_t cap, int3
     // one step current -> spare buffers (the state itself is left as it is)
     auto launch = [&](const StepShape& sh) {
         if (s->two)
-            return launch_step2c(s->q, (const float*)s->f[s->cur], (const float*)s->fv[s->cur],
-                                 (float*)s->f[s->cur ^ 1], (float*)s->fv[s->cur ^ 1], a2, sh,
-                                 s->stream);
+            return launch_step2c(s->q, s->p.storage, s->f[s->cur], s->fv[s->cur],
+                                 s->f[s->cur ^ 1], s->fv[s->cur ^ 1], a2, sh, s->stream);
         a.planes = sh.tile_z;
         return launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a, sh,
                            s->stream);

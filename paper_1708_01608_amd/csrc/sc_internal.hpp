@@ -54,14 +54,17 @@ struct Step2cArgs {
     int planes;  // set by launch_step2c from the shape
     int64_t N;
     double tau_l, tau_v, Gx;
+    double ref_l, ref_v;  // storage shifts of the two components (0 with FP32 storage)
 };
 bool step2c_shape_supported(int q, const StepShape& s);
-hipError_t launch_step2c(int q, const float* src_l, const float* src_v, float* dst_l,
-                         float* dst_v, const Step2cArgs& a, const StepShape& s, hipStream_t st);
+// FP32 storage runs FP64 arithmetic, FP16 / BF16 storage FP32 arithmetic.
+hipError_t launch_step2c(int q, int storage, const void* src_l, const void* src_v, void* dst_l,
+                         void* dst_v, const Step2cArgs& a, const StepShape& s, hipStream_t st);
 // Reported fields of the mixture: rho_l, rho_v (FP32) and the barycentric velocity; dens holds
 // [2][N] FP64 densities afterwards.
-hipError_t launch_fields2c(int q, const float* f_l, const float* f_v, double* dens, float* rho_l,
-                           float* rho_v, float* u, const Step2cArgs& a, hipStream_t st);
+hipError_t launch_fields2c(int q, int storage, const void* f_l, const void* f_v, double* dens,
+                           float* rho_l, float* rho_v, float* u, const Step2cArgs& a,
+                           hipStream_t st);
 
 // Barrier fix-up of the listed frontier nodes after a step (same src/dst as that step).
 hipError_t launch_barrier_fix(int q, int storage, int compute, const void* src, void* dst,
@@ -100,6 +103,7 @@ struct FieldArgs {
     // interaction; pressures then follow p = (rho_l + rho_v)/3 + (Gx/3) rho_l rho_v
     const void* f2;
     double Gx;
+    double rho_ref2;  // storage shift of the gas component
 };
 hipError_t launch_psi(int q, int storage, const void* f, double* psi, const FieldArgs& a,
                       hipStream_t st);

@@ -54,9 +54,9 @@ __device__ __forceinline__ float dev_sum_f(const S* f, int64_t n, const FieldArg
     return s;
 }
 
-// FP64 density of node n: rho_ref + sum of the stored deviations, summed in double.
+// Sum of the stored deviations of node n, in double.
 template <int Q, typename S>
-__device__ __forceinline__ double rho_d(const S* f, int64_t n, const FieldArgs& a)
+__device__ __forceinline__ double dev_d(const S* f, int64_t n, const FieldArgs& a)
 {
     int x, y, z;
     coords3(n, a.nx, a.ny, x, y, z);
@@ -64,17 +64,24 @@ __device__ __forceinline__ double rho_d(const S* f, int64_t n, const FieldArgs& 
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         s += (double)load_f(f[(int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a)]);
-    return a.rho_ref_d + s;
+    return s;
+}
+
+// FP64 density of node n: rho_ref + sum of the stored deviations.
+template <int Q, typename S>
+__device__ __forceinline__ double rho_d(const S* f, int64_t n, const FieldArgs& a)
+{
+    return a.rho_ref_d + dev_d<Q, S>(f, n, a);
 }
 
 // EOS pressure at node n: one component, p = rho/3 + (G/6) psi^2; two components (the gas
-// component in a.f2, FP32), p = (rho_l + rho_v)/3 + (Gx/3) rho_l rho_v.
+// component in a.f2, same storage, shifted by a.rho_ref2), p = (rho_l + rho_v)/3 + (Gx/3) rho_l rho_v.
 template <int Q, typename S>
 __device__ __forceinline__ double pressure_at(const S* f, int64_t n, const FieldArgs& a)
 {
     const double r = rho_d<Q, S>(f, n, a);
     if (a.f2) {
-        const double rv = rho_d<Q, float>((const float*)a.f2, n, a);
+        const double rv = a.rho_ref2 + dev_d<Q, S>((const S*)a.f2, n, a);
         return (r + rv) / 3.0 + (a.Gx / 3.0) * r * rv;
     }
     return pressure_d(r, a.Gd);

@@ -42,8 +42,8 @@ def main():
         "two_bubble": (W.two_bubble, [("f32", "f64"), ("f32", "f32")]),
         "foam_3d_large": (W.foam_3d_large, [("f32", "f64"), ("f32", "f32"), ("f16", "f32"),
                                             ("bf16", "f32")]),
-        "mixture_2d": (W.mixture_2d, [("f32", "f64")]),
-        "mixture_3d": (W.mixture_3d, [("f32", "f64")]),
+        "mixture_2d": (W.mixture_2d, [("f32", "f64"), ("f16", "f32"), ("bf16", "f32")]),
+        "mixture_3d": (W.mixture_3d, [("f32", "f64"), ("f16", "f32"), ("bf16", "f32")]),
     }
     for name in args.workloads.split(","):
         make, combos = plan[name]

@@ -124,9 +124,8 @@ def test_gravity_parameters_are_checked(lib, g, storage, variant, code):
 
 @pytest.mark.parametrize("field,value,code", [
     ("components", 3, sc.SC_E_INVAL), ("rho_vapour", 0.0, sc.SC_E_INVAL),
-    ("tau_vapour", 0.5, sc.SC_E_INVAL), ("storage", 1, sc.SC_E_UNSUPPORTED),
-    ("compute", 1, sc.SC_E_UNSUPPORTED), ("barrier", 1, sc.SC_E_UNSUPPORTED),
-    ("rho_ref", 1.0, sc.SC_E_UNSUPPORTED), ("step_variant", 2, sc.SC_E_INVAL),
+    ("tau_vapour", 0.5, sc.SC_E_INVAL), ("compute", 1, sc.SC_E_UNSUPPORTED),
+    ("barrier", 1, sc.SC_E_UNSUPPORTED), ("step_variant", 2, sc.SC_E_INVAL),
     ("tile_x", 32, sc.SC_E_INVAL),
 ])
 def test_two_component_parameters_are_checked(lib, field, value, code):
@@ -138,6 +137,25 @@ def test_two_component_parameters_are_checked(lib, field, value, code):
     h = C.c_void_p()
     assert lib.sc_create(C.byref(p), C.byref(h)) == code
     assert not h.value
+
+
+@pytest.mark.parametrize("storage,compute,rho_ref,ok", [
+    (0, 0, -1.0, True), (0, 2, 1.0, True), (0, 1, -1.0, False),
+    (1, 0, -1.0, True), (2, 1, -1.0, True), (1, 2, -1.0, False), (2, 2, 1.0, False),
+])
+def test_two_component_storage_pairings(lib, storage, compute, rho_ref, ok):
+    # FP32 storage runs FP64 arithmetic, 16-bit storage FP32 arithmetic; any shift is accepted
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    p.components, p.storage, p.compute, p.rho_ref = 2, storage, compute, rho_ref
+    h = C.c_void_p()
+    rc = lib.sc_create(C.byref(p), C.byref(h))
+    if ok:
+        assert rc in (sc.SC_OK, sc.SC_E_DEVICE, sc.SC_E_NOMEM)
+        if h.value:
+            lib.sc_destroy(h)
+    else:
+        assert rc == sc.SC_E_UNSUPPORTED and not h.value
 
 
 def test_boxes_past_32bit_byte_offsets_are_rejected(lib):

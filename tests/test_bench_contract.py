@@ -34,7 +34,24 @@ def test_counter_summary_is_used_only_for_the_profiled_kernel_and_tile():
         assert bench.traffic_from_profile("foam_3d", "f32", "f64", tile) == d["hbm_bytes_per_launch"]
     other = (tile[0] // 2,) + tile[1:]
     assert bench.traffic_from_profile("foam_3d", "f32", "f64", other) is None
-    assert bench.traffic_from_profile("foam_3d", "f16", "f32", tile) is None
+    # each storage type has its own counter summary
+    assert bench.traffic_from_profile("foam_3d", "bf16", "f32", tile) is None
+    with open(os.path.join(ROOT, "profiles", "step_counters_foam_3d_f16_f32.json")) as fh:
+        d16 = json.load(fh)
+    assert d16["hbm_bytes_per_launch"] < d["hbm_bytes_per_launch"]
+    if d16["kernel_hash"] == bench.step_kernel_hash():
+        assert bench.traffic_from_profile("foam_3d", "f16", "f32", tuple(d16["tile"])) == \
+            d16["hbm_bytes_per_launch"]
+
+
+def test_mixture_storage_pairings_are_checked_before_any_gpu_work():
+    # FP32 storage pairs with FP64 arithmetic, 16-bit storage with FP32
+    for st, comp in (("f16", "f64"), ("f32", "f32")):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload",
+                            "mixture_3d", "--storage", st, "--compute", comp],
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2
+        assert "mixture" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
 
 
 @pytest.mark.gpu

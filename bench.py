@@ -269,7 +269,7 @@ def run_batch(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU path (slab "
+        print(json.dumps({"error": "the library runs on one GPU; the multi-GPU path (slab "
                                    "domain decomposition) is a design note, not code",
                           "n_gpus": args.gpus}))
         sys.exit(2)

@@ -40,7 +40,7 @@ typedef enum sc_status {
     SC_E_DEVICE = -3,      /* a HIP call failed (handle latched) */
     SC_E_STATE = -4,       /* handle latched by an earlier failure, or call out of order */
     SC_E_NUMERIC = -5,     /* a global FP64 total was not finite (handle latched) */
-    SC_E_UNSUPPORTED = -6  /* valid request this build does not provide */
+    SC_E_UNSUPPORTED = -6  /* valid request the library does not provide */
 } sc_status;
 
 enum { SC_D2Q9 = 9, SC_D3Q19 = 19 };

@@ -4,18 +4,18 @@
 // lattice, Sec. 3 and 3.1): the force on component a is F_a = -Gx rho_a(x) sum_i w_i rho_b(x+e_i)
 // e_i (b the other component); both relax to equilibria at the common velocity
 //   u' = sum_a (j_a / tau_a) / sum_a (rho_a / tau_a),  u_a^eq = u' + tau_a F_a / rho_a,
-// then stream.  Storage: FP32 populations unshifted with FP64 arithmetic, or FP16 / BF16
-// populations shifted by w_i rho_ref per component (the liquid's rho_ref, the gas component's
-// dissolved density) with FP32 arithmetic.  Densities travel as deviations from the shift: the
+// then stream.  Storage: FP32 populations with FP64 arithmetic (unshifted unless rho_ref is
+// set), or FP16 / BF16 populations with FP32 arithmetic; shifted storage holds f_i - w_i rho_ref
+// per component (the liquid's rho_ref, the gas component's dissolved density).  Densities travel as deviations from the shift: the
 // interaction sums need only differences (sum_i w_i e_i = 0), and the shift is added back where
 // the density itself enters.
 //
 // One fused kernel per step, built like the one-component marching kernels: a block owns a tile
 // of one plane (a row segment in 2D, an x-y tile in 3D) and marches along the remaining axis.
 // The densities of both components over the tile and its one-node ring, for three planes, live
-// in LDS (FP64); the tile's own populations of both components stay in registers from their
-// load until the collision one plane later.  Each plane of both components is read once and
-// written once: 2 x 2 Q x 4 bytes per node and step.
+// in LDS (in the arithmetic type); the tile's own populations of both components stay in
+// registers from their load until the collision one plane later.  Each plane of both components
+// is read once and written once: 2 x 2 Q x sizeof(storage) bytes per node and step.
 #include <algorithm>
 
 #include "sc_device.hpp"
@@ -26,8 +26,8 @@ namespace sc {
 
 namespace {
 
-// Momentum j = sum_i g_i e_i of one component (stored values are the populations themselves).
-// (The shift w_i rho_ref of stored values drops out: sum_i w_i e_i = 0.)
+// Momentum j = sum_i g_i e_i of one component from its stored values (the shift w_i rho_ref
+// drops out: sum_i w_i e_i = 0).
 template <int Q, typename A>
 __device__ __forceinline__ void momentum(const float* g, A& jx, A& jy, A& jz)
 {

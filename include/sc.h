@@ -197,6 +197,13 @@ int sc_step(struct sc_sim* sim, int32_t nsteps);
  * post-streaming populations in a fixed order. */
 int sc_fields(struct sc_sim* sim, float* rho, float* u, double* totals);
 
+/* The same rho and u, written into the caller's device memory (rho_dev: N floats, u_dev: d x N
+ * floats, SoA; either may be NULL) on the sim's stream; returns after the stream work completes.
+ * The buffers stay the caller's.  A pointer that is not memory of the sim's device, or whose
+ * allocation ends before the fields do, is SC_E_INVAL before any kernel runs.  (An allocator that
+ * sub-allocates, as torch's does, reports its whole segment: the caller must size sub-buffers.) */
+int sc_fields_device(struct sc_sim* sim, float* rho_dev, float* u_dev);
+
 /* Sec. 3.1 EOS and the criterion's operator, in FP64: p = rho/3 + (G/6) psi^2 and
  * lap[x] = 6 sum_{i != 0} w_i (p(x + e_i) - p(x)). */
 int sc_laplacian_p(struct sc_sim* sim, double* p, double* lap);

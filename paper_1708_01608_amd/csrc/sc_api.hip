@@ -1105,31 +1105,60 @@ int sc_step(sc_sim* s, int32_t nsteps)
     return SC_OK;
 }
 
+// Reported fields into device buffers rho_d[N] and u_d[d][N] (either may be NULL), queued on
+// the sim's stream: the liquid density and the mixture's barycentric velocity with two
+// components, rho and (j + F/2)/rho with one.
+static int fields_to_device(sc_sim* s, float* rho_d, float* u_d)
+{
+    if (!rho_d && !u_d) return SC_OK;
+    if (s->two) {
+        HIPX(launch_fields2c(s->q, s->p.storage, s->f[s->cur], s->fv[s->cur],
+                             (double*)s->dens2.p, rho_d, nullptr, u_d, step2c_args(s), s->stream));
+        return SC_OK;
+    }
+    const FieldArgs fa = field_args(s);
+    TRY(ensure(s, s->psi, sizeof(double) * (size_t)s->N));
+    HIPX(launch_psi(s->q, s->p.storage, s->f[s->cur], (double*)s->psi.p, fa, s->stream));
+    HIPX(launch_fields(s->q, s->p.storage, s->f[s->cur], (const double*)s->psi.p, rho_d, u_d, fa,
+                       s->stream));
+    return SC_OK;
+}
+
+// A caller's device buffer of `bytes` bytes: memory of the sim's device whose allocation covers
+// [p, p + bytes).  A host pointer or one of another device is rejected before any kernel sees it.
+static int check_device_buffer(const void* p, size_t bytes, const char* what)
+{
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SC_E_INVAL, std::string(what) + " is not device memory");
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SC_E_DEVICE, "hipGetDevice failed");
+    }
+    if (at.type != hipMemoryTypeDevice || at.device != dev)
+        return fail(SC_E_INVAL, std::string(what) + " is not memory of the sim's device");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SC_E_INVAL, std::string(what) + ": no allocation range");
+    }
+    if ((const char*)p + bytes > (const char*)base + size)
+        return fail(SC_E_INVAL, std::string(what) + " is smaller than the fields it must hold");
+    return SC_OK;
+}
+
 int sc_fields(sc_sim* s, float* rho, float* u, double* totals)
 {
     TRY(check_usable(s));
-    const FieldArgs fa = field_args(s);
-    if ((rho || u) && s->two) {  // liquid density and the mixture's barycentric velocity
+    if (rho || u) {
         if (rho) TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
         if (u) TRY(ensure(s, s->u_out, sizeof(float) * (size_t)s->N * s->d));
-        HIPX(launch_fields2c(s->q, s->p.storage, s->f[s->cur], s->fv[s->cur],
-                             (double*)s->dens2.p, rho ? (float*)s->rho_out.p : nullptr, nullptr,
-                             u ? (float*)s->u_out.p : nullptr, step2c_args(s), s->stream));
-        if (rho)
-            HIPX(hipMemcpyAsync(rho, s->rho_out.p, sizeof(float) * (size_t)s->N,
-                                hipMemcpyDeviceToHost, s->stream));
-        if (u)
-            HIPX(hipMemcpyAsync(u, s->u_out.p, sizeof(float) * (size_t)s->N * s->d,
-                                hipMemcpyDeviceToHost, s->stream));
-        HIPX(hipStreamSynchronize(s->stream));
-    } else if (rho || u) {
-        TRY(ensure(s, s->psi, sizeof(double) * (size_t)s->N));
-        if (rho) TRY(ensure(s, s->rho_out, sizeof(float) * (size_t)s->N));
-        if (u) TRY(ensure(s, s->u_out, sizeof(float) * (size_t)s->N * s->d));
-        HIPX(launch_psi(s->q, s->p.storage, s->f[s->cur], (double*)s->psi.p, fa, s->stream));
-        HIPX(launch_fields(s->q, s->p.storage, s->f[s->cur], (const double*)s->psi.p,
-                           rho ? (float*)s->rho_out.p : nullptr, u ? (float*)s->u_out.p : nullptr,
-                           fa, s->stream));
+        TRY(fields_to_device(s, rho ? (float*)s->rho_out.p : nullptr,
+                             u ? (float*)s->u_out.p : nullptr));
         if (rho)
             HIPX(hipMemcpyAsync(rho, s->rho_out.p, sizeof(float) * (size_t)s->N,
                                 hipMemcpyDeviceToHost, s->stream));
@@ -1139,6 +1168,16 @@ int sc_fields(sc_sim* s, float* rho, float* u, double* totals)
         HIPX(hipStreamSynchronize(s->stream));
     }
     if (totals) TRY(totals_now(s, totals));
+    return SC_OK;
+}
+
+int sc_fields_device(sc_sim* s, float* rho_dev, float* u_dev)
+{
+    TRY(check_usable(s));
+    if (rho_dev) TRY(check_device_buffer(rho_dev, sizeof(float) * (size_t)s->N, "rho"));
+    if (u_dev) TRY(check_device_buffer(u_dev, sizeof(float) * (size_t)s->N * s->d, "u"));
+    TRY(fields_to_device(s, rho_dev, u_dev));
+    HIPX(hipStreamSynchronize(s->stream));
     return SC_OK;
 }
 

@@ -97,7 +97,8 @@ class BatchResult(C.Structure):
 # Entry points declared in include/sc.h (checked by the CPU test suite).
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
-    "sc_seed_nuclei", "sc_step", "sc_fields", "sc_laplacian_p", "sc_label_bubbles",
+    "sc_seed_nuclei", "sc_step", "sc_fields", "sc_fields_device", "sc_laplacian_p",
+    "sc_label_bubbles",
     "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei",
     "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density",
     "sc_set_gas_equilibrium", "sc_time",
@@ -134,6 +135,7 @@ def load_library(path=LIB_PATH):
         "sc_seed_nuclei": (C.c_int, [P, C.c_int32, P, P, P, C.c_double]),
         "sc_step": (C.c_int, [P, C.c_int32]),
         "sc_fields": (C.c_int, [P, P, P, P]),
+        "sc_fields_device": (C.c_int, [P, P, P]),
         "sc_laplacian_p": (C.c_int, [P, P, P]),
         "sc_label_bubbles": (C.c_int, [P, P, P, P]),
         "sc_merge_events": (C.c_int, [P, P, C.c_int32, P]),
@@ -340,6 +342,28 @@ class Sim:
         tot = np.zeros(4) if totals else None
         _check(self._lib.sc_fields(self._h, _ptr(r), _ptr(uu), _ptr(tot)))
         return r, uu, tot
+
+    def fields_device(self, rho=None, u=None):
+        """rho and u into caller-owned torch tensors on the sim's device (float32, contiguous,
+        N and (d, N) elements); None skips one.  Returns (rho, u)."""
+        import torch
+
+        for t, n, name in ((rho, self.N, "rho"), (u, self.d * self.N, "u")):
+            if t is None:
+                continue
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and
+                    t.is_contiguous() and t.numel() == n):
+                raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} "
+                                 "elements")
+        # the tensors' pending work on the caller's stream comes first; the call itself returns
+        # after the sim's stream has finished
+        if self.mem is not None:
+            self.mem.stream.wait_stream(torch.cuda.current_stream())
+        else:
+            torch.cuda.current_stream().synchronize()
+        _check(self._lib.sc_fields_device(self._h, None if rho is None else rho.data_ptr(),
+                                          None if u is None else u.data_ptr()))
+        return rho, u
 
     def totals(self):
         return self.fields(rho=False, u=False, totals=True)[2]

@@ -427,12 +427,23 @@ int schedule_chunk_len(const sc_sim* s)
 }
 
 // ---- test pass (Fig. 1 step 7; Sec. 3.1 eta_m) ------------------------------------------------
-int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uint8_t* mask_host)
+// With tot_host (and no caller mask) the FP64 totals come from the same sweep of populations as
+// the mask; the gas component's, with two components, are added from a sweep of its own.
+int gas_totals_add(sc_sim* s, double out[4]);
+int totals_now(sc_sim* s, double out[4]);
+
+int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uint8_t* mask_host,
+                  double* tot_host = nullptr)
 {
     const FieldArgs fa = field_args(s);
     TRY(ensure(s, s->parent, sizeof(uint32_t) * (size_t)s->N));
     TRY(ensure(s, s->small, 4096));
-    if (mask_host) {
+    double* out_d = (double*)s->small.p;
+    if (tot_host && !mask_host) {
+        TRY(ensure(s, s->partials, sizeof(double) * 4 * (size_t)totals_blocks(s->N)));
+        HIPX(launch_mask_totals(s->q, s->p.storage, s->f[s->cur], (uint32_t*)s->parent.p,
+                                (double*)s->partials.p, out_d, fa, s->stream));
+    } else if (mask_host) {
         TRY(ensure(s, s->mask8, (size_t)s->N));
         HIPX(hipMemcpyAsync(s->mask8.p, mask_host, (size_t)s->N, hipMemcpyHostToDevice,
                             s->stream));
@@ -446,11 +457,15 @@ int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uin
     uint32_t* ncomp_d = (uint32_t*)((char*)s->small.p + 64);
     HIPX(launch_fill_i32((int32_t*)ncomp_d, 0, 1, s->stream));
     HIPX(launch_flatten((uint32_t*)s->parent.p, labels_d, ncomp_d, s->N, s->stream));
-    if (ncomp_host) {
+    if (ncomp_host)
         HIPX(hipMemcpyAsync(ncomp_host, ncomp_d, sizeof(uint32_t), hipMemcpyDeviceToHost,
                             s->stream));
-        HIPX(hipStreamSynchronize(s->stream));
-    }
+    if (tot_host && !mask_host)
+        HIPX(hipMemcpyAsync(tot_host, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                            s->stream));
+    if (ncomp_host || tot_host) HIPX(hipStreamSynchronize(s->stream));
+    if (tot_host && !mask_host && s->two) TRY(gas_totals_add(s, tot_host));
+    if (tot_host && mask_host) TRY(totals_now(s, tot_host));
     return SC_OK;
 }
 
@@ -464,17 +479,24 @@ int totals_now(sc_sim* s, double out[4])
                        s->stream));
     HIPX(hipMemcpyAsync(out, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPX(hipStreamSynchronize(s->stream));
-    if (s->two) {  // the mixture's totals: both components
-        double gas[4];
-        FieldArgs fg = fa;
-        fg.rho_ref_d = s->rho_ref_v;
-        fg.rho_ref = (float)s->rho_ref_v;
-        HIPX(launch_totals(s->q, s->p.storage, s->fv[s->cur], (double*)s->partials.p, out_d, fg,
-                           s->stream));
-        HIPX(hipMemcpyAsync(gas, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-        HIPX(hipStreamSynchronize(s->stream));
-        for (int c = 0; c < 4; ++c) out[c] += gas[c];
-    }
+    if (s->two) TRY(gas_totals_add(s, out));  // the mixture's totals: both components
+    return SC_OK;
+}
+
+int gas_totals_add(sc_sim* s, double out[4])
+{
+    FieldArgs fg = field_args(s);
+    fg.rho_ref_d = s->rho_ref_v;
+    fg.rho_ref = (float)s->rho_ref_v;
+    TRY(ensure(s, s->partials, sizeof(double) * 4 * (size_t)totals_blocks(s->N)));
+    TRY(ensure(s, s->small, 4096));
+    double* out_d = (double*)s->small.p;
+    double gas[4];
+    HIPX(launch_totals(s->q, s->p.storage, s->fv[s->cur], (double*)s->partials.p, out_d, fg,
+                       s->stream));
+    HIPX(hipMemcpyAsync(gas, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    for (int c = 0; c < 4; ++c) out[c] += gas[c];
     return SC_OK;
 }
 
@@ -552,11 +574,9 @@ int test_pass(sc_sim* s, bool with_criterion)
     TRY(prof_begin(s, SC_KERNEL_TEST, &pe));
 
     TRY(ensure(s, s->labels, sizeof(uint32_t) * (size_t)s->N));
-    TRY(label_current(s, (uint32_t*)s->labels.p, nullptr, nullptr));
-    s->have_labels = true;
-
     double tot[4];
-    TRY(totals_now(s, tot));
+    TRY(label_current(s, (uint32_t*)s->labels.p, nullptr, nullptr, tot));
+    s->have_labels = true;
     const bool finite = std::isfinite(tot[0]) && std::isfinite(tot[1]) &&
                         std::isfinite(tot[2]) && std::isfinite(tot[3]);
 

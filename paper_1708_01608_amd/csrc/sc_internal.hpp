@@ -119,6 +119,10 @@ hipError_t launch_totals(int q, int storage, const void* f, double* partials, do
                          const FieldArgs& a, hipStream_t st);
 
 // Labelling: parent[N] (uint32, 0xffffffff = liquid), labels[N] (1 + root, 0 = liquid).
+// Gas mask (as launch_mask_from_rho) and the FP64 totals (as launch_totals, into out_d[4]) from
+// one sweep of the populations.
+hipError_t launch_mask_totals(int q, int storage, const void* f, uint32_t* parent,
+                              double* partials, double* out_d, const FieldArgs& a, hipStream_t st);
 hipError_t launch_mask_from_rho(int q, int storage, const void* f, uint32_t* parent,
                                 const FieldArgs& a, hipStream_t st);
 hipError_t launch_mask_from_bytes(const uint8_t* mask_d, uint32_t* parent, int64_t N,

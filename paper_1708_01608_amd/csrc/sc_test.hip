@@ -218,11 +218,20 @@ __global__ void __launch_bounds__(256) k_totals(const S* f, double* partials, Fi
 
 __global__ void k_totals_final(const double* partials, int nb, double* out, double base_mass)
 {
-    // one thread per component, blocks summed in index order
+    // one thread per component, blocks summed in index order; the loads of 16 partials are
+    // issued together before their ordered adds, so the sum waits out one latency per 16
     const int c = threadIdx.x;
     if (c >= 4) return;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partials[(int64_t)b * 4 + c];
+    int b = 0;
+    for (; b + 16 <= nb; b += 16) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = partials[(int64_t)(b + k) * 4 + c];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += v[k];
+    }
+    for (; b < nb; ++b) s += partials[(int64_t)b * 4 + c];
     out[c] = (c == 0) ? base_mass + s : s;
 }
 
@@ -235,6 +244,47 @@ __global__ void k_mask_rho(const S* f, uint32_t* parent, FieldArgs a)
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
          n += (int64_t)gridDim.x * blockDim.x)
         parent[n] = (rho_d<Q, S>(f, n, a) < a.theta) ? (uint32_t)n : kLiquid;
+}
+
+// The test pass's mask and FP64 totals from one sweep of pulled populations: parent[n] exactly as
+// k_mask_rho (same density, same order of the sum), and per block the partial sums of the pulled
+// values and their momenta, as k_totals forms them from the stored values (the pulled values are a
+// permutation of the stored ones, so the totals are the same sums in another order).
+template <int Q, typename S>
+__global__ void __launch_bounds__(256) k_mask_totals(const S* f, uint32_t* parent,
+                                                     double* partials, FieldArgs a)
+{
+    using L = lat<Q>;
+    double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+        double s = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double g = (double)load_f(f[(int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a)]);
+            s += g;
+            sx += g * L::ex[i];
+            sy += g * L::ey[i];
+            sz += g * L::ez[i];
+        }
+        parent[n] = (a.rho_ref_d + s < a.theta) ? (uint32_t)n : kLiquid;
+        m += s;
+        jx += sx;
+        jy += sy;
+        jz += sz;
+    }
+    __shared__ double red[4][4];
+    m = wave_sum(m); jx = wave_sum(jx); jy = wave_sum(jy); jz = wave_sum(jz);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { red[w][0] = m; red[w][1] = jx; red[w][2] = jy; red[w][3] = jz; }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int k = 0; k < 4; ++k) t += red[k][threadIdx.x];
+        partials[(int64_t)blockIdx.x * 4 + threadIdx.x] = t;
+    }
 }
 
 __global__ void k_mask_bytes(const uint8_t* mask, uint32_t* parent, int64_t N)
@@ -708,6 +758,20 @@ hipError_t launch_mask_from_rho(int q, int storage, const void* f, uint32_t* par
     SC_DISPATCH(q, storage,
                 hipLaunchKernelGGL((k_mask_rho<QQ, SS>), grid_for(a.N), dim3(256), 0, st,
                                    (const SS*)f, parent, a));
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_totals(int q, int storage, const void* f, uint32_t* parent,
+                              double* partials, double* out_d, const FieldArgs& a, hipStream_t st)
+{
+    const int nb = totals_blocks(a.N);
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_mask_totals<QQ, SS>), dim3(nb), dim3(256), 0, st,
+                                   (const SS*)f, parent, partials, a));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, partials, nb, out_d,
+                       (double)a.N * a.rho_ref_d);
     return hipGetLastError();
 }
 

@@ -89,3 +89,49 @@ def test_full_batch_merge_steps_match_oracle_on_sampled_boxes():
     topo = sum(1 for m, tp, _ in ora if m < 0 and tp >= 0)
     print(f"sample: {fired} criterion merges, {topo} topological first, mismatches {mism}")
     assert not mism
+
+
+def _spec_of(sizes, radii, gaps, G=-5.0, max_steps=60, K=10):
+    n = len(sizes)
+    Gs = np.full(n, G)
+    rg, rl = np.zeros(n), np.zeros(n)
+    for k in range(n):
+        rg[k], rl[k] = W.coexistence_densities(Gs[k])
+    return W.BatchSpec(nx=np.array([s[0] for s in sizes]), ny=np.array([s[1] for s in sizes]),
+                       G=Gs, radius=np.asarray(radii, float), gap=np.asarray(gaps),
+                       rho_l=rl, rho_g=rg, seed=np.arange(7, 7 + n, dtype=np.int64),
+                       max_steps=max_steps, K=K)
+
+
+def test_batch_edge_sizes_match_oracle():
+    """Boxes below the workload's 64-node minimum (a block of rows then wraps the box more than
+    once) and the widest box (256 nodes, one row per block) in one launch; every node after 60
+    steps without a test pass inside the horizon."""
+    spec = _spec_of([(24, 20), (30, 26), (256, 300)], [4.0, 5.0, 30.0], [2, 3, 4], K=1000)
+    print("[gpu] batch edge sizes 24x20, 30x26, 256x300, 60 steps", flush=True)
+    b = sc.Batch(spec)
+    res, _ = b.run()
+    for k in range(spec.n):
+        s = spec.instance(k)
+        assert res[k]["steps_run"] == 60
+        o = OracleSim(9, s.nx, s.ny, 1, s.tau, s.G, s.rho_l, s.rho_g, s.amp, s.seed, 0.0, 0, 8)
+        o.seed_nuclei(s.centres, s.radii, s.budgets, 0.0)
+        o.step(60)
+        ro, _, _ = o.fields()
+        err = float(np.max(np.abs(b.density(k).astype(np.float64) - ro) / ro))
+        print(f"box {k} {s.nx}x{s.ny}: rho err {err:.2e}")
+        assert err <= 1e-5
+
+
+def test_single_box_batch_merge_steps_match_oracle():
+    """A batch of one box: one workgroup, test passes every 10 steps, the stopping rule."""
+    spec = _spec_of([(96, 80)], [18.0], [4], max_steps=1000)  # the oracle fires at t = 620
+    print("[gpu] batch of one box 96x80, up to 1000 steps", flush=True)
+    b = sc.Batch(spec)
+    res, _ = b.run()
+    _, m, tp, t = oracle_run(spec.instance(0), spec.max_steps)
+    g = res[0]
+    print(f"gpu merge {g['merge_step']} topo {g['topo_step']} run {g['steps_run']} | "
+          f"oracle merge {m} topo {tp} run {t}")
+    assert (g["merge_step"], g["topo_step"], g["steps_run"]) == (m, tp, t)
+    assert t < spec.max_steps  # the pair merges inside the horizon

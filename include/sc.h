@@ -201,7 +201,8 @@ int sc_fields(struct sc_sim* sim, float* rho, float* u, double* totals);
  * floats, SoA; either may be NULL) on the sim's stream; returns after the stream work completes.
  * The buffers stay the caller's.  A pointer that is not memory of the sim's device, or whose
  * allocation ends before the fields do, is SC_E_INVAL before any kernel runs.  (An allocator that
- * sub-allocates, as torch's does, reports its whole segment: the caller must size sub-buffers.) */
+ * sub-allocates, as torch's does, reports its whole segment: the caller must size sub-buffers.
+ * Memory whose allocation range HIP cannot report, such as virtual-memory mappings, is refused.) */
 int sc_fields_device(struct sc_sim* sim, float* rho_dev, float* u_dev);
 
 /* Sec. 3.1 EOS and the criterion's operator, in FP64: p = rho/3 + (G/6) psi^2 and

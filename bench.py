@@ -364,12 +364,14 @@ def main():
     print(json.dumps(out), flush=True)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
-    if args.variants and comps == 1:
-        for storage, compute in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
+    if args.variants:
+        # the mixture pairs 16-bit storage with FP32 arithmetic only
+        combos = ((("f32", "f32"),) if comps == 1 else ()) + (("f16", "f32"), ("bf16", "f32"))
+        for storage, compute in combos:
             if args.barrier and storage != "f32":
                 continue  # the barrier runs on FP32 storage only
             rv = run_gpu(spec, args, storage, compute, args.steps, args.warmup, tile)
-            b = (bytes_per_node(spec.q, storage) + (2 if args.barrier else 0)) * spec.N
+            b = (bytes_per_node(spec.q, storage, comps) + (2 if args.barrier else 0)) * spec.N
             a = b / (rv["step_ms"] / 1e3 / max(rv["launches"], 1)) / 1e9
             print(json.dumps({"variant": f"{storage} storage / {compute} compute",
                               "workload": spec.name,

@@ -342,7 +342,9 @@ int prof_begin(sc_sim* s, int cls, hipEvent_t* out_b)
             *e = s->pool.back();
             s->pool.pop_back();
         } else {
-            HIPX(hipEventCreate(e));
+            // timing only: no system-scope fence (cache writeback) at each record, which
+            // would cost every profiled launch several microseconds
+            HIPX(hipEventCreateWithFlags(e, hipEventDisableSystemFence));
         }
     }
     HIPX(hipEventRecord(r.a, s->stream));

@@ -209,6 +209,22 @@ def test_pressure_laplacian_eigenvalue(q, shape, k):
 
 
 # ------------------------------------------------------------------------------------------
+# The EOS coefficient read back from the oracle's pressure on uniform states: G cs^2 / 2 = G / 6
+# (the reading of the truncated value), which the paper prints as 0.166 (Sec. 3.1).
+# ------------------------------------------------------------------------------------------
+def test_eos_coefficient_matches_the_printed_value():
+    with open(os.path.join(GOLDEN, "paper_eos_coefficient.txt")) as fh:
+        printed = float([l for l in fh if l.strip() and not l.startswith("#")][0])
+    for G, rho in ((-5.0, 1.93), (-4.5, 0.7), (-5.5, 0.16)):
+        o = OracleSim(9, 8, 8, 1, tau=1.0, G=G, rho_l=rho, rho_g=rho, amp=0.0, K=0)
+        p, _ = o.laplacian_p()
+        psi = 1.0 - np.exp(-rho)
+        c = (p[0] - rho / 3.0) / (G * psi * psi)
+        assert abs(c - 1.0 / 6.0) < 1e-12
+        assert math.floor(c * 1000) / 1000 == printed  # truncated to the printed digits
+
+
+# ------------------------------------------------------------------------------------------
 # P6: flat-interface coexistence against the mechanical-stability condition.
 # ------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("G", [-4.5, -5.0, -5.5])

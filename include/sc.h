@@ -93,7 +93,8 @@ typedef struct sc_params {
      * that the criterion has not merged with the node's contributes psi(rho_liquid) instead of
      * its own psi.  Owners are rebuilt at every test pass after its merges; only the nodes next
      * to another bubble's node are affected, and they are re-stepped by a fix-up kernel after
-     * every step.  FP32 storage only (SC_E_UNSUPPORTED otherwise); at most 65534 nuclei. */
+     * every step.  Any storage (16-bit storage with FP32 arithmetic; FP64 arithmetic there is
+     * SC_E_UNSUPPORTED); at most 65534 nuclei. */
     int32_t barrier;           /* 0 off (default), 1 on */
     int32_t corona;            /* liquid layers a bubble owns, 0..64 (default 3) */
     /* Gravity for drainage studies (the paper's runs leave it out): a body force

@@ -831,8 +831,8 @@ int validate(const sc_params* p)
     if (p->barrier != 0 && p->barrier != 1) return fail(SC_E_INVAL, "barrier must be 0 or 1");
     if (p->barrier && (p->corona < 0 || p->corona > 64))
         return fail(SC_E_INVAL, "corona must be in [0, 64]");
-    if (p->barrier && p->storage != SC_STORE_F32)
-        return fail(SC_E_UNSUPPORTED, "the barrier is offered on FP32 storage only");
+    if (p->barrier && p->storage != SC_STORE_F32 && p->compute == SC_COMPUTE_F64)
+        return fail(SC_E_UNSUPPORTED, "the barrier on 16-bit storage runs FP32 arithmetic");
     if (p->components != 1 && p->components != 2) return fail(SC_E_INVAL, "components must be 1 or 2");
     if (p->components == 2) {
         if (!std::isfinite(p->G_cross)) return fail(SC_E_INVAL, "G_cross must be finite");

@@ -415,13 +415,29 @@ hipError_t launch_barrier_fix(int q, int storage, int compute, const void* src, 
                               const StepArgs& a, const uint32_t* list, int count, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (storage != SC_STORE_F32 || !a.owner) return hipErrorInvalidValue;
+    if (!a.owner) return hipErrorInvalidValue;
     const dim3 grid((unsigned)std::min(65535, (count + 255) / 256)), block(256);
+    const bool g = a.grav != 0;
+    if (storage != SC_STORE_F32) {
+        // 16-bit storage: FP32 arithmetic, no gravity (its extended kernels are FP32-storage only)
+        if (compute == SC_COMPUTE_F64 || g) return hipErrorInvalidValue;
+#define SC_FIX16(QQ, SS)                                                                         \
+    hipLaunchKernelGGL((k_barrier_fix<QQ, SS, float, false>), grid, block, 0, st, (const SS*)src, \
+                       (SS*)dst, a, list, count)
+        if (storage == SC_STORE_F16) {
+            if (q == 9) SC_FIX16(9, _Float16); else SC_FIX16(19, _Float16);
+        } else if (storage == SC_STORE_BF16) {
+            if (q == 9) SC_FIX16(9, __bf16); else SC_FIX16(19, __bf16);
+        } else {
+            return hipErrorInvalidValue;
+        }
+#undef SC_FIX16
+        return hipGetLastError();
+    }
     const float* s = (const float*)src;
     float* d = (float*)dst;
 #define SC_FIX(QQ, AA, EE) \
     hipLaunchKernelGGL((k_barrier_fix<QQ, float, AA, EE>), grid, block, 0, st, s, d, a, list, count)
-    const bool g = a.grav != 0;
     if (compute == SC_COMPUTE_F64) {
         if (q == 9) { if (g) SC_FIX(9, double, true); else SC_FIX(9, double, false); }
         else { if (g) SC_FIX(19, double, true); else SC_FIX(19, double, false); }

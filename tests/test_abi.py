@@ -94,7 +94,6 @@ def test_invalid_parameters_are_rejected_before_any_device_work(lib, field, valu
 
 @pytest.mark.parametrize("field,value,code", [
     ("corona", -1, sc.SC_E_INVAL), ("corona", 65, sc.SC_E_INVAL), ("barrier", 2, sc.SC_E_INVAL),
-    ("storage", 1, sc.SC_E_UNSUPPORTED),
 ])
 def test_barrier_parameters_are_checked(lib, field, value, code):
     p = sc.Params()
@@ -105,6 +104,21 @@ def test_barrier_parameters_are_checked(lib, field, value, code):
     h = C.c_void_p()
     assert lib.sc_create(C.byref(p), C.byref(h)) == code
     assert not h.value
+
+
+@pytest.mark.parametrize("storage,compute,ok", [(1, 0, True), (2, 1, True), (1, 2, False)])
+def test_barrier_on_16bit_storage_runs_fp32_arithmetic(lib, storage, compute, ok):
+    p = sc.Params()
+    lib.sc_params_init(C.byref(p))
+    p.barrier, p.storage, p.compute = 1, storage, compute
+    h = C.c_void_p()
+    rc = lib.sc_create(C.byref(p), C.byref(h))
+    if ok:
+        assert rc in (sc.SC_OK, sc.SC_E_DEVICE, sc.SC_E_NOMEM)
+        if h.value:
+            lib.sc_destroy(h)
+    else:
+        assert rc == sc.SC_E_UNSUPPORTED and not h.value
 
 
 @pytest.mark.parametrize("g,storage,variant,code", [

@@ -100,8 +100,8 @@ typedef struct sc_params {
     /* Gravity for drainage studies (the paper's runs leave it out): a body force
      * (rho - rho0) g is added to the Shan-Chen force of every node, in the step and in the
      * reported velocity.  rho0 = rho_buoyancy if > 0, else the mean density of the box, taken at
-     * sc_create and again at sc_seed_nuclei (no net force on the periodic box).  FP32 storage
-     * only (SC_E_UNSUPPORTED otherwise, and with step_variant 2); gravity[2] is ignored in 2D. */
+     * sc_create and again at sc_seed_nuclei (no net force on the periodic box).  Any storage;
+     * SC_E_UNSUPPORTED with step_variant 2; gravity[2] is ignored in 2D. */
     double gravity[3];         /* g in lattice units; all zero (default) = off */
     double rho_buoyancy;       /* rho0; <= 0 selects the mean density */
     /* Two components (Sec. 3: the agent's gas raises bubble volume; Sec. 3.1: two simulations

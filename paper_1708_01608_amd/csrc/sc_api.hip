@@ -855,8 +855,6 @@ int validate(const sc_params* p)
     {
         const bool g_on = p->gravity[0] != 0.0 || p->gravity[1] != 0.0 ||
                           (p->lattice == SC_D3Q19 && p->gravity[2] != 0.0);
-        if (g_on && p->storage != SC_STORE_F32)
-            return fail(SC_E_UNSUPPORTED, "gravity is offered on FP32 storage only");
         if (g_on && p->step_variant == 2)
             return fail(SC_E_UNSUPPORTED, "gravity has no software-pipelined kernel");
     }

@@ -419,11 +419,17 @@ hipError_t launch_barrier_fix(int q, int storage, int compute, const void* src, 
     const dim3 grid((unsigned)std::min(65535, (count + 255) / 256)), block(256);
     const bool g = a.grav != 0;
     if (storage != SC_STORE_F32) {
-        // 16-bit storage: FP32 arithmetic, no gravity (its extended kernels are FP32-storage only)
-        if (compute == SC_COMPUTE_F64 || g) return hipErrorInvalidValue;
+        // 16-bit storage: FP32 arithmetic
+        if (compute == SC_COMPUTE_F64) return hipErrorInvalidValue;
 #define SC_FIX16(QQ, SS)                                                                         \
-    hipLaunchKernelGGL((k_barrier_fix<QQ, SS, float, false>), grid, block, 0, st, (const SS*)src, \
-                       (SS*)dst, a, list, count)
+    do {                                                                                         \
+        if (g)                                                                                   \
+            hipLaunchKernelGGL((k_barrier_fix<QQ, SS, float, true>), grid, block, 0, st,         \
+                               (const SS*)src, (SS*)dst, a, list, count);                        \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_barrier_fix<QQ, SS, float, false>), grid, block, 0, st,        \
+                               (const SS*)src, (SS*)dst, a, list, count);                        \
+    } while (0)
         if (storage == SC_STORE_F16) {
             if (q == 9) SC_FIX16(9, _Float16); else SC_FIX16(19, _Float16);
         } else if (storage == SC_STORE_BF16) {
@@ -486,23 +492,19 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
     const int nb = g.gx * g.gy * g.gz;
     g.remap = (nb % 8 == 0) ? 1 : 0;
     dim3 grid(nb);
-    // the extended kernels (gravity) exist for FP32 storage (either arithmetic), marching
-    // variants only
-    constexpr bool kBarOK = std::is_same<S, float>::value;
+    // the extended kernels (gravity) exist for the marching variants only
     const bool ext = a.grav != 0;
-    if (ext && (!kBarOK || s.variant == 2)) return hipErrorInvalidValue;
+    if (ext && s.variant == 2) return hipErrorInvalidValue;
 #define SC_L2(TX)                                                                                \
     if (s.tile_x == TX) {                                                                        \
-        if constexpr (kBarOK) {                                                                  \
-            if (ext) {                                                                           \
-                if (s.variant == 3)                                                              \
-                    hipLaunchKernelGGL((k_step2d<S, A, TX, true, true>), grid, dim3(TX), 0, st,  \
-                                       src, dst, a, g);                                          \
-                else                                                                             \
-                    hipLaunchKernelGGL((k_step2d<S, A, TX, false, true>), grid, dim3(TX), 0, st, \
-                                       src, dst, a, g);                                          \
-                return hipGetLastError();                                                        \
-            }                                                                                    \
+        if (ext) {                                                                               \
+            if (s.variant == 3)                                                                  \
+                hipLaunchKernelGGL((k_step2d<S, A, TX, true, true>), grid, dim3(TX), 0, st,      \
+                                   src, dst, a, g);                                              \
+            else                                                                                 \
+                hipLaunchKernelGGL((k_step2d<S, A, TX, false, true>), grid, dim3(TX), 0, st,     \
+                                   src, dst, a, g);                                              \
+            return hipGetLastError();                                                            \
         }                                                                                        \
         if (s.variant == 3)                                                                      \
             hipLaunchKernelGGL((k_step2d<S, A, TX, true>), grid, dim3(TX), 0, st, src, dst, a,   \
@@ -513,16 +515,14 @@ static hipError_t step_typed(int q, const S* src, S* dst, const StepArgs& a, con
     }
 #define SC_L3(TX, TY)                                                                            \
     if (s.tile_x == TX && s.tile_y == TY) {                                                      \
-        if constexpr (kBarOK) {                                                                  \
-            if (ext) {                                                                           \
-                if (s.variant == 3)                                                              \
-                    hipLaunchKernelGGL((k_step3d<S, A, TX, TY, true, true>), grid,               \
-                                       dim3(TX * TY), 0, st, src, dst, a, g);                    \
-                else                                                                             \
-                    hipLaunchKernelGGL((k_step3d<S, A, TX, TY, false, true>), grid,              \
-                                       dim3(TX * TY), 0, st, src, dst, a, g);                    \
-                return hipGetLastError();                                                        \
-            }                                                                                    \
+        if (ext) {                                                                               \
+            if (s.variant == 3)                                                                  \
+                hipLaunchKernelGGL((k_step3d<S, A, TX, TY, true, true>), grid,                   \
+                                   dim3(TX * TY), 0, st, src, dst, a, g);                        \
+            else                                                                                 \
+                hipLaunchKernelGGL((k_step3d<S, A, TX, TY, false, true>), grid,                  \
+                                   dim3(TX * TY), 0, st, src, dst, a, g);                        \
+            return hipGetLastError();                                                            \
         }                                                                                        \
         if (s.variant == 2)                                                                      \
             hipLaunchKernelGGL((k_step3d_pipe<S, A, TX, TY>), grid, dim3(TX * TY), 0, st, src,   \

@@ -122,18 +122,28 @@ def test_barrier_on_16bit_storage_runs_fp32_arithmetic(lib, storage, compute, ok
 
 
 @pytest.mark.parametrize("g,storage,variant,code", [
-    ((float("nan"), 0.0, 0.0), 0, 0, sc.SC_E_INVAL), ((0.0, 1e-5, 0.0), 2, 0, sc.SC_E_UNSUPPORTED),
+    ((float("nan"), 0.0, 0.0), 0, 0, sc.SC_E_INVAL), ((0.0, 1e-5, 0.0), 0, 2, sc.SC_E_UNSUPPORTED),
+    ((0.0, 1e-5, 0.0), 2, 0, None), ((0.0, 0.0, -1e-5), 1, 3, None),
 ])
 def test_gravity_parameters_are_checked(lib, g, storage, variant, code):
+    # D3Q19 (the pipelined variant 2 exists there); any storage; None: accepted by validation
     p = sc.Params()
     lib.sc_params_init(C.byref(p))
     assert list(p.gravity) == [0.0, 0.0, 0.0] and p.rho_buoyancy == 0.0
+    p.lattice, p.nx, p.ny, p.nz = 19, 32, 32, 32
     for c in range(3):
         p.gravity[c] = g[c]
     p.storage, p.step_variant = storage, variant
+    if variant:
+        p.tile_x, p.tile_y, p.tile_z = 32, 4, 8
     h = C.c_void_p()
-    assert lib.sc_create(C.byref(p), C.byref(h)) == code
-    assert not h.value
+    rc = lib.sc_create(C.byref(p), C.byref(h))
+    if code is None:
+        assert rc in (sc.SC_OK, sc.SC_E_DEVICE, sc.SC_E_NOMEM)
+        if h.value:
+            lib.sc_destroy(h)
+    else:
+        assert rc == code and not h.value
 
 
 @pytest.mark.parametrize("field,value,code", [

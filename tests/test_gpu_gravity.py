@@ -79,3 +79,49 @@ def test_gravity_tiles_and_variants_bitwise_equal(q):
             ref = f
         assert np.array_equal(f, ref), (tx, ty, tz, v)
         s.close()
+
+
+# ---- 16-bit storage (FP32 arithmetic) ----------------------------------------------------------
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("case", ["two_bubble", "spheres_barrier"])
+def test_gravity_16bit_storage_against_oracle(case, storage):
+    from parity import TOL
+
+    if case == "two_bubble":
+        spec, g, barrier, steps = W.two_bubble(), (0.0, -2e-5), False, 100
+    else:
+        spec = W.SimSpec(name="spheres", q=19, nx=44, ny=24, nz=24, tau=0.9, G=-5.0, rho_l=1.93,
+                         rho_g=0.16, amp=1e-3, seed=3, K=10, steps=50,
+                         centres=np.array([(10.5, 11.5, 11.5), (32.5, 11.5, 11.5)]),
+                         radii=np.array([7.0, 7.0]), budgets=np.zeros(2), rate=0.0)
+        g, barrier, steps = (1e-5, 0.0, -3e-5), True, 50
+    _announce(f"gravity {case} {steps} steps, storage {storage}")
+    o, gpu = _pair(spec, g, barrier, storage=storage)
+    # rho0 is the mean density of the seeded box, summed from the shifted 16-bit values
+    drho0 = abs(gpu.rho0 - o.rho0) / o.rho0
+    gpu.step(steps)
+    o.step(steps)
+    e_rho, e_u, _, _ = field_errors(gpu, o)
+    print(f"{storage}: rho {e_rho:.3e} u {e_u:.3e} rho0 rel diff {drho0:.2e}")
+    rt, ut = TOL[(storage, "f32")]
+    assert e_rho <= rt and e_u <= ut
+    assert drho0 <= (1e-5 if storage == "f16" else 1e-3)  # measured 1.5e-6 and 1.7e-4
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_gravity_16bit_tiles_bitwise_equal(storage):
+    spec = W.SimSpec(name="spheres", q=19, nx=44, ny=24, nz=24, tau=0.9, G=-5.0, rho_l=1.93,
+                     rho_g=0.16, amp=1e-3, seed=3, K=10, steps=30,
+                     centres=np.array([(10.5, 11.5, 11.5), (29.5, 11.5, 11.5)]),
+                     radii=np.array([7.0, 7.0]), budgets=np.zeros(2), rate=0.0)
+    _announce(f"gravity tiles, storage {storage}")
+    ref = None
+    for tx, ty, tz, v in [(32, 4, 5, 1), (64, 8, 16, 3), (256, 4, 64, 3)]:
+        s = gpu_from_spec(spec, gravity=(0.0, 2e-5, -3e-5), tile=(tx, ty, tz), variant=v,
+                          storage=storage)
+        s.step(30)
+        f = s.get_populations()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), (tx, ty, tz, v)
+        s.close()

@@ -16,8 +16,8 @@ def _announce(msg):
     print(f"[gpu] {msg}", flush=True)
 
 
-def _sim(components):
-    kw = dict(q=19, nx=40, ny=24, nz=20, tau=0.9, amp=1e-3, seed=3, K=10)
+def _sim(components, storage="f32"):
+    kw = dict(q=19, nx=40, ny=24, nz=20, tau=0.9, amp=1e-3, seed=3, K=10, storage=storage)
     if components == 2:
         g = sc.Sim(G=0.0, rho_l=1.0, rho_g=0.05, two_component=TC, **kw)
     else:
@@ -27,12 +27,13 @@ def _sim(components):
     return g
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("components", [1, 2])
-def test_fields_device_equals_fields(components):
+def test_fields_device_equals_fields(components, storage):
     import torch
 
-    _announce(f"fields_device components={components}")
-    g = _sim(components)
+    _announce(f"fields_device components={components} storage={storage}")
+    g = _sim(components, storage)
     g.step(30)
     rho = torch.full((g.N,), float("nan"), device="cuda", dtype=torch.float32)
     u = torch.full((g.d, g.N), float("nan"), device="cuda", dtype=torch.float32)

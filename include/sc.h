@@ -210,6 +210,10 @@ int sc_fields_device(struct sc_sim* sim, float* rho_dev, float* u_dev);
  * lap[x] = 6 sum_{i != 0} w_i (p(x + e_i) - p(x)). */
 int sc_laplacian_p(struct sc_sim* sim, double* p, double* lap);
 
+/* The same p and lap written into the caller's device memory (N doubles each; either may be
+ * NULL), with the buffer checks of sc_fields_device. */
+int sc_laplacian_p_device(struct sc_sim* sim, double* p_dev, double* lap_dev);
+
 /* Canonical labels of a gas mask: label = 1 + smallest linear index of the component, 0 for
  * liquid; connectivity = the lattice neighbours (8 in 2D, 18 in 3D), periodic.  mask[N] (nonzero =
  * gas) or NULL for rho < gas_threshold on the current state.  *ncomp receives the component

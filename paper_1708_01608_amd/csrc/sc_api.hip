@@ -1222,6 +1222,24 @@ int sc_laplacian_p(sc_sim* s, double* p, double* lap)
     return SC_OK;
 }
 
+int sc_laplacian_p_device(sc_sim* s, double* p_dev, double* lap_dev)
+{
+    TRY(check_usable(s));
+    if (!p_dev && !lap_dev) return SC_OK;
+    if (p_dev) TRY(check_device_buffer(p_dev, sizeof(double) * (size_t)s->N, "p"));
+    if (lap_dev) TRY(check_device_buffer(lap_dev, sizeof(double) * (size_t)s->N, "lap"));
+    const FieldArgs fa = field_args(s);
+    double* p_d = p_dev;
+    if (!p_d) {  // the Laplacian alone still needs p
+        TRY(ensure(s, s->p_out, sizeof(double) * (size_t)s->N));
+        p_d = (double*)s->p_out.p;
+    }
+    HIPX(launch_pressure(s->q, s->p.storage, s->f[s->cur], p_d, fa, s->stream));
+    if (lap_dev) HIPX(launch_laplacian(s->q, p_d, lap_dev, fa, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
 int sc_label_bubbles(sc_sim* s, const uint8_t* mask, uint32_t* labels, int64_t* ncomp)
 {
     TRY(check_usable(s));

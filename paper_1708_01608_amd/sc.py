@@ -98,7 +98,7 @@ class BatchResult(C.Structure):
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
     "sc_seed_nuclei", "sc_step", "sc_fields", "sc_fields_device", "sc_laplacian_p",
-    "sc_label_bubbles",
+    "sc_laplacian_p_device", "sc_label_bubbles",
     "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei",
     "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density",
     "sc_set_gas_equilibrium", "sc_time",
@@ -137,6 +137,7 @@ def load_library(path=LIB_PATH):
         "sc_fields": (C.c_int, [P, P, P, P]),
         "sc_fields_device": (C.c_int, [P, P, P]),
         "sc_laplacian_p": (C.c_int, [P, P, P]),
+        "sc_laplacian_p_device": (C.c_int, [P, P, P]),
         "sc_label_bubbles": (C.c_int, [P, P, P, P]),
         "sc_merge_events": (C.c_int, [P, P, C.c_int32, P]),
         "sc_topo_events": (C.c_int, [P, P, C.c_int32, P]),
@@ -372,6 +373,26 @@ class Sim:
         p = np.zeros(self.N)
         lap = np.zeros(self.N)
         _check(self._lib.sc_laplacian_p(self._h, _ptr(p), _ptr(lap)))
+        return p, lap
+
+    def laplacian_p_device(self, p=None, lap=None):
+        """p and its lattice Laplacian into caller-owned float64 torch tensors of N elements on
+        the sim's device; None skips one.  Returns (p, lap)."""
+        import torch
+
+        for t, name in ((p, "p"), (lap, "lap")):
+            if t is None:
+                continue
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and
+                    t.is_contiguous() and t.numel() == self.N):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of "
+                                 f"{self.N} elements")
+        if self.mem is not None:
+            self.mem.stream.wait_stream(torch.cuda.current_stream())
+        else:
+            torch.cuda.current_stream().synchronize()
+        _check(self._lib.sc_laplacian_p_device(self._h, None if p is None else p.data_ptr(),
+                                               None if lap is None else lap.data_ptr()))
         return p, lap
 
     def label_bubbles(self, mask=None):

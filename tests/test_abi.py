@@ -206,6 +206,7 @@ def test_null_handles(lib):
     assert lib.sc_destroy(None) == sc.SC_E_INVAL
     assert lib.sc_fields(None, None, None, None) == sc.SC_E_INVAL
     assert lib.sc_fields_device(None, None, None) == sc.SC_E_INVAL
+    assert lib.sc_laplacian_p_device(None, None, None) == sc.SC_E_INVAL
 
 
 @pytest.mark.parametrize("q", [9, 19])

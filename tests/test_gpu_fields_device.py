@@ -66,3 +66,22 @@ def test_fields_device_refuses_other_memory():
     assert b"device" in g._lib.sc_last_error()
     assert not torch.any(pinned)
     g.step(5)  # the handle stays usable
+
+
+@pytest.mark.parametrize("components", [1, 2])
+def test_laplacian_p_device_equals_host(components):
+    import torch
+
+    _announce(f"laplacian_p_device components={components}")
+    g = _sim(components)
+    g.step(20)
+    p_h, lap_h = g.laplacian_p()
+    p = torch.full((g.N,), float("nan"), device="cuda", dtype=torch.float64)
+    lap = torch.full((g.N,), float("nan"), device="cuda", dtype=torch.float64)
+    g.laplacian_p_device(p, lap)
+    assert np.array_equal(p.cpu().numpy(), p_h) and np.array_equal(lap.cpu().numpy(), lap_h)
+    lap2 = torch.zeros(g.N, device="cuda", dtype=torch.float64)
+    g.laplacian_p_device(lap=lap2)  # the Laplacian alone
+    assert np.array_equal(lap2.cpu().numpy(), lap_h)
+    with pytest.raises(ValueError):
+        g.laplacian_p_device(p=torch.zeros(g.N, device="cuda", dtype=torch.float32))

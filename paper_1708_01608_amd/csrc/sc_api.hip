@@ -50,6 +50,7 @@ struct sc_sim {
     int64_t N = 0;
     double theta = 0.0, rho_ref = 0.0;
     double rho_ref_v = 0.0;  // storage shift of the gas component (0 when the liquid's is 0)
+    double pass_tot[4] = {0.0, 0.0, 0.0, 0.0};  // test-pass totals (target of a queued copy)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     size_t es = 4;
@@ -430,12 +431,14 @@ int schedule_chunk_len(const sc_sim* s)
 
 // ---- test pass (Fig. 1 step 7; Sec. 3.1 eta_m) ------------------------------------------------
 // With tot_host (and no caller mask) the FP64 totals come from the same sweep of populations as
-// the mask; the gas component's, with two components, are added from a sweep of its own.
+// the mask; the gas component's, with two components, are added from a sweep of its own.  With
+// defer, the totals' copy is only queued: the caller synchronizes the stream and adds the gas
+// component's totals itself.
 int gas_totals_add(sc_sim* s, double out[4]);
 int totals_now(sc_sim* s, double out[4]);
 
 int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uint8_t* mask_host,
-                  double* tot_host = nullptr)
+                  double* tot_host = nullptr, bool defer = false)
 {
     const FieldArgs fa = field_args(s);
     TRY(ensure(s, s->parent, sizeof(uint32_t) * (size_t)s->N));
@@ -465,8 +468,8 @@ int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uin
     if (tot_host && !mask_host)
         HIPX(hipMemcpyAsync(tot_host, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost,
                             s->stream));
-    if (ncomp_host || tot_host) HIPX(hipStreamSynchronize(s->stream));
-    if (tot_host && !mask_host && s->two) TRY(gas_totals_add(s, tot_host));
+    if (ncomp_host || (tot_host && !defer)) HIPX(hipStreamSynchronize(s->stream));
+    if (tot_host && !mask_host && s->two && !defer) TRY(gas_totals_add(s, tot_host));
     if (tot_host && mask_host) TRY(totals_now(s, tot_host));
     return SC_OK;
 }
@@ -576,11 +579,11 @@ int test_pass(sc_sim* s, bool with_criterion)
     TRY(prof_begin(s, SC_KERNEL_TEST, &pe));
 
     TRY(ensure(s, s->labels, sizeof(uint32_t) * (size_t)s->N));
-    double tot[4];
-    TRY(label_current(s, (uint32_t*)s->labels.p, nullptr, nullptr, tot));
+    // the totals' copy and the nucleus map below share one synchronization; the copy goes to
+    // the sim's own array, which outlives an early return
+    double* tot = s->pass_tot;
+    TRY(label_current(s, (uint32_t*)s->labels.p, nullptr, nullptr, tot, true));
     s->have_labels = true;
-    const bool finite = std::isfinite(tot[0]) && std::isfinite(tot[1]) &&
-                        std::isfinite(tot[2]) && std::isfinite(tot[3]);
 
     // nucleus map: label at each nucleus node
     s->comp.assign((size_t)n, 0u);
@@ -594,8 +597,11 @@ int test_pass(sc_sim* s, bool with_criterion)
                                   s->stream));
         HIPX(hipMemcpyAsync(s->comp.data(), comp_d, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
                             s->stream));
-        HIPX(hipStreamSynchronize(s->stream));
     }
+    HIPX(hipStreamSynchronize(s->stream));
+    if (s->two) TRY(gas_totals_add(s, tot));
+    const bool finite = std::isfinite(tot[0]) && std::isfinite(tot[1]) &&
+                        std::isfinite(tot[2]) && std::isfinite(tot[3]);
 
     // bubbles: distinct nonzero labels held by nuclei, ascending
     std::vector<uint32_t> distinct;

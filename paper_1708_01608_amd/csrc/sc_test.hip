@@ -256,24 +256,41 @@ __global__ void __launch_bounds__(256) k_mask_totals(const S* f, uint32_t* paren
 {
     using L = lat<Q>;
     double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        int x, y, z;
-        coords3(n, a.nx, a.ny, x, y, z);
-        double s = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    // two nodes per pass, loads of both first (one block carries many nodes, so each pass would
+    // otherwise wait out a full memory latency); the sums keep the node order
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t n0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n0 < a.N; n0 += 2 * stride) {
+        float g[2][Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double g = (double)load_f(f[(int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a)]);
-            s += g;
-            sx += g * L::ex[i];
-            sy += g * L::ey[i];
-            sz += g * L::ez[i];
+        for (int u = 0; u < 2; ++u) {
+            const int64_t n = n0 + u * stride;
+            if (n < a.N) {
+                int x, y, z;
+                coords3(n, a.nx, a.ny, x, y, z);
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    g[u][i] = load_f(f[(int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a)]);
+            }
         }
-        parent[n] = (a.rho_ref_d + s < a.theta) ? (uint32_t)n : kLiquid;
-        m += s;
-        jx += sx;
-        jy += sy;
-        jz += sz;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t n = n0 + u * stride;
+            if (n >= a.N) continue;
+            double s = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double v = (double)g[u][i];
+                s += v;
+                sx += v * L::ex[i];
+                sy += v * L::ey[i];
+                sz += v * L::ez[i];
+            }
+            parent[n] = (a.rho_ref_d + s < a.theta) ? (uint32_t)n : kLiquid;
+            m += s;
+            jx += sx;
+            jy += sy;
+            jz += sz;
+        }
     }
     __shared__ double red[4][4];
     m = wave_sum(m); jx = wave_sum(jx); jy = wave_sum(jy); jz = wave_sum(jz);

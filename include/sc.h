@@ -194,8 +194,11 @@ int sc_seed_nuclei(struct sc_sim* sim, int32_t n, const double* centre, const do
  * FP64 totals).  nsteps >= 0.  SC_E_NUMERIC if a total is not finite. */
 int sc_step(struct sc_sim* sim, int32_t nsteps);
 
-/* rho[N] and u[d][N] = (j + F/2)/rho (FP32), totals = (M, Jx, Jy, Jz) summed in FP64 over the
- * post-streaming populations in a fixed order. */
+/* Fig. 1 steps 8-9 (the lattices merged to post-process the output; Sec. 3.1 model): rho[N] and
+ * u[d][N] = (j + F/2)/rho (FP32; F with the body force when gravity is on; the mixture reports
+ * its barycentric velocity), totals = (M, Jx, Jy, Jz) summed in FP64 over the post-streaming
+ * populations in a fixed order.  Host arrays, caller-owned; any of the three may be NULL.
+ * Errors: SC_E_INVAL (NULL sim), SC_E_STATE (after a device or numeric error), SC_E_DEVICE. */
 int sc_fields(struct sc_sim* sim, float* rho, float* u, double* totals);
 
 /* The same rho and u, written into the caller's device memory (rho_dev: N floats, u_dev: d x N
@@ -214,10 +217,12 @@ int sc_laplacian_p(struct sc_sim* sim, double* p, double* lap);
  * NULL), with the buffer checks of sc_fields_device. */
 int sc_laplacian_p_device(struct sc_sim* sim, double* p_dev, double* lap_dev);
 
-/* Canonical labels of a gas mask: label = 1 + smallest linear index of the component, 0 for
- * liquid; connectivity = the lattice neighbours (8 in 2D, 18 in 3D), periodic.  mask[N] (nonzero =
- * gas) or NULL for rho < gas_threshold on the current state.  *ncomp receives the component
- * count.  Does not change the bubble registry. */
+/* Fig. 1 step 7 (the new bubbles' size comes from the gas phase separated from the fluid, steps
+ * 2 and 7): canonical labels of a gas mask: label = 1 + smallest linear index of the component,
+ * 0 for liquid; connectivity = the lattice neighbours (8 in 2D, 18 in 3D), periodic.  mask[N]
+ * (host, nonzero = gas) or NULL for rho < gas_threshold on the current state; labels[N] (host,
+ * caller-owned).  *ncomp receives the component count.  Does not change the bubble registry.
+ * Errors: SC_E_INVAL (NULL sim or labels), SC_E_STATE, SC_E_DEVICE. */
 int sc_label_bubbles(struct sc_sim* sim, const uint8_t* mask, uint32_t* labels, int64_t* ncomp);
 
 /* Registry of the last test pass and of all passes so far.  *n_total receives the full count;

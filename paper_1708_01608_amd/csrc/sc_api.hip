@@ -1177,6 +1177,18 @@ static int check_device_buffer(const void* p, size_t bytes, const char* what)
     return SC_OK;
 }
 
+// Two output ranges [a, a + na) and [b, b + nb) of one call must not overlap: the kernels read
+// neighbours of what they write (the Laplacian reads p around the node whose lap it stores), so
+// overlapping outputs would race.
+static int check_disjoint(const void* a, size_t na, const void* b, size_t nb, const char* what)
+{
+    if (!a || !b) return SC_OK;
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    if (pa < pb + nb && pb < pa + na) return fail(SC_E_INVAL, std::string(what) + " overlap");
+    return SC_OK;
+}
+
 int sc_fields(sc_sim* s, float* rho, float* u, double* totals)
 {
     TRY(check_usable(s));
@@ -1202,6 +1214,8 @@ int sc_fields_device(sc_sim* s, float* rho_dev, float* u_dev)
     TRY(check_usable(s));
     if (rho_dev) TRY(check_device_buffer(rho_dev, sizeof(float) * (size_t)s->N, "rho"));
     if (u_dev) TRY(check_device_buffer(u_dev, sizeof(float) * (size_t)s->N * s->d, "u"));
+    TRY(check_disjoint(rho_dev, sizeof(float) * (size_t)s->N, u_dev,
+                       sizeof(float) * (size_t)s->N * s->d, "rho and u"));
     TRY(fields_to_device(s, rho_dev, u_dev));
     HIPX(hipStreamSynchronize(s->stream));
     return SC_OK;
@@ -1234,6 +1248,8 @@ int sc_laplacian_p_device(sc_sim* s, double* p_dev, double* lap_dev)
     if (!p_dev && !lap_dev) return SC_OK;
     if (p_dev) TRY(check_device_buffer(p_dev, sizeof(double) * (size_t)s->N, "p"));
     if (lap_dev) TRY(check_device_buffer(lap_dev, sizeof(double) * (size_t)s->N, "lap"));
+    TRY(check_disjoint(p_dev, sizeof(double) * (size_t)s->N, lap_dev,
+                       sizeof(double) * (size_t)s->N, "p and lap"));
     const FieldArgs fa = field_args(s);
     double* p_d = p_dev;
     if (!p_d) {  // the Laplacian alone still needs p

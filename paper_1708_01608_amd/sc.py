@@ -247,6 +247,17 @@ def _tuned_shape(q, nx, ny, nz, storage, compute, variant, components=1):
     return tuple(e["tile"]), e["variant"]
 
 
+def _check_disjoint(a, b, what):
+    """Two output tensors of one call must not share memory: the kernels read neighbours of the
+    nodes they write, so overlapping outputs would race (the library checks the same)."""
+    if a is None or b is None:
+        return
+    a0, a1 = a.data_ptr(), a.data_ptr() + a.numel() * a.element_size()
+    b0, b1 = b.data_ptr(), b.data_ptr() + b.numel() * b.element_size()
+    if a0 < b1 and b0 < a1:
+        raise ValueError(f"{what} overlap")
+
+
 class Sim:
     """One periodic Shan-Chen box on the GPU (a handle of libsc)."""
 
@@ -356,6 +367,7 @@ class Sim:
                     t.is_contiguous() and t.numel() == n):
                 raise ValueError(f"{name} must be a contiguous float32 device tensor of {n} "
                                  "elements")
+        _check_disjoint(rho, u, "rho and u")
         # the tensors' pending work on the caller's stream comes first; the call itself returns
         # after the sim's stream has finished
         if self.mem is not None:
@@ -387,6 +399,7 @@ class Sim:
                     t.is_contiguous() and t.numel() == self.N):
                 raise ValueError(f"{name} must be a contiguous float64 device tensor of "
                                  f"{self.N} elements")
+        _check_disjoint(p, lap, "p and lap")
         if self.mem is not None:
             self.mem.stream.wait_stream(torch.cuda.current_stream())
         else:

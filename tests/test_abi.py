@@ -246,3 +246,28 @@ def test_two_component_tiles_are_checked(lib, q, tile, variant, ok):
             lib.sc_destroy(h)
     else:
         assert rc == sc.SC_E_INVAL
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in the binding's host-side overlap check."""
+
+    def __init__(self, ptr, n, size):
+        self._p, self._n, self._s = ptr, n, size
+
+    def data_ptr(self):
+        return self._p
+
+    def numel(self):
+        return self._n
+
+    def element_size(self):
+        return self._s
+
+
+def test_binding_refuses_overlapping_outputs():
+    a = _FakeTensor(0x10000, 100, 8)
+    sc._check_disjoint(a, _FakeTensor(0x10000 + 800, 100, 8), "p and lap")   # adjacent: fine
+    sc._check_disjoint(a, None, "p and lap")
+    for start in (0x10000, 0x10000 + 8, 0x10000 - 8 * 99, 0x10000 + 799):
+        with pytest.raises(ValueError):
+            sc._check_disjoint(a, _FakeTensor(start, 100, 8), "p and lap")

@@ -85,3 +85,27 @@ def test_laplacian_p_device_equals_host(components):
     assert np.array_equal(lap2.cpu().numpy(), lap_h)
     with pytest.raises(ValueError):
         g.laplacian_p_device(p=torch.zeros(g.N, device="cuda", dtype=torch.float32))
+
+
+def test_device_outputs_that_overlap_are_refused():
+    import torch
+
+    _announce("device outputs overlap")
+    g = _sim(1)
+    g.step(5)
+    buf = torch.zeros(2 * g.N, device="cuda", dtype=torch.float64)
+    # the same memory as p and lap: refused by the binding and, underneath it, by the library
+    with pytest.raises(ValueError):
+        g.laplacian_p_device(buf[: g.N], buf[: g.N])
+    rc = g._lib.sc_laplacian_p_device(g._h, C.c_void_p(buf.data_ptr()),
+                                      C.c_void_p(buf.data_ptr() + 8 * (g.N // 2)))
+    assert rc == sc.SC_E_INVAL and b"overlap" in g._lib.sc_last_error()
+    assert not torch.any(buf)
+    f = torch.zeros((g.d + 1) * g.N, device="cuda", dtype=torch.float32)
+    rc = g._lib.sc_fields_device(g._h, C.c_void_p(f.data_ptr() + 4), C.c_void_p(f.data_ptr()))
+    assert rc == sc.SC_E_INVAL and b"overlap" in g._lib.sc_last_error()
+    # adjacent, disjoint halves are fine
+    g.laplacian_p_device(buf[: g.N], buf[g.N:])
+    p_h, lap_h = g.laplacian_p()
+    assert np.array_equal(buf[: g.N].cpu().numpy(), p_h)
+    assert np.array_equal(buf[g.N:].cpu().numpy(), lap_h)

@@ -247,6 +247,52 @@ def test_flat_interface_coexistence(G):
     assert abs(gas - rg) < 0.5 * abs(gas - mg)
 
 
+# P6 (velocity): a converged flat interface is at rest, so the velocity the model reports
+# vanishes there while the interaction force does not.  With velocity-shift forcing every
+# collision adds F to the momentum; the momentum halfway through the forcing, j + F/2, is the
+# one that vanishes at rest (j = -F/2 before a collision, +F/2 after it).  Reporting j/rho or
+# (j + F)/rho would leave |F|/(2 rho) ~ 0.12 at the interface.  The painted step profile leaves
+# the lattice's period-2 (staggered) mode ringing at ~5e-3, so u is averaged over two
+# consecutive steps, which cancels that mode.
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+def test_reported_velocity_vanishes_at_a_flat_interface(tau):
+    G = -5.0
+    rg, rl, _ = T.coexistence(G)
+    nx, ny = 128, 4
+    o = OracleSim(9, nx, ny, 1, tau=tau, G=G, rho_l=rl, rho_g=rg, amp=0.0, K=0)
+    x = np.arange(nx)
+    o.set_equilibrium(np.tile(np.where((x >= 32) & (x < 96), rl, rg), ny))
+    o.step(40000)
+    _, u1, _ = o.fields()
+    o.step(1)
+    rho, u2, _ = o.fields()
+    half_force = np.abs(o.force()[0] / (2.0 * rho)).max()
+    assert half_force >= 0.1
+    assert np.abs(0.5 * (u1 + u2)).max() <= 1e-6
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+def test_mixture_velocity_vanishes_at_a_flat_interface(tau):
+    # the same statement for the two-component mixture: its barycentric velocity
+    # (j_l + j_v + (F_l + F_v)/2) / (rho_l + rho_v) vanishes on a converged flat liquid/gas slab
+    # while the total cross force (F_l + F_v)/(2 rho) is ~0.016 (tau = 1) to 0.038 (tau = 0.8)
+    nx, ny = 128, 4
+    o = OracleSim(9, nx, ny, 1, tau=tau, G=0.0, rho_l=1.0, rho_g=0.05, amp=0.0, K=0,
+                  two_component=(1.5, tau, 1.0, 0.05))
+    x = np.tile(np.arange(nx), ny)
+    liquid = (x >= 32) & (x < 96)
+    o.set_equilibrium(np.where(liquid, 1.0, 0.05))
+    o.set_gas_equilibrium(np.where(liquid, 0.05, 1.0))
+    o.step(40000)
+    _, u1, _ = o.fields()
+    o.step(1)
+    rho_l, u2, _ = o.fields()
+    rho = rho_l + o.gas_density()
+    half_force = np.abs(o.force()[0] / (2.0 * rho)).max()
+    assert half_force >= 0.01
+    assert np.abs(0.5 * (u1 + u2)).max() <= 1e-7
+
+
 def test_flat_interface_3d_matches_2d():
     G = -5.0
     rg, rl, _ = T.coexistence(G)

@@ -233,6 +233,16 @@ int sc_bubbles(struct sc_sim* sim, sc_bubble* out, int32_t cap, int32_t* n_total
 int sc_last_labels(struct sc_sim* sim, uint32_t* labels);
 /* comp[n]: label of each nucleus's node at the last pass (0: not gas); remaining[n]: budgets. */
 int sc_nuclei(struct sc_sim* sim, uint32_t* comp, double* remaining);
+/* Sec. 3 (gas added to every bubble each step until the agent is spent): the agent's mass
+ * ledger, FP64.  *released = sum_k (budget_k - remaining_k), the mass the nuclei have given up;
+ * *undelivered = the part of it the populations have not taken yet.  Each step the source adds
+ * to a fed bubble what it is owed (earlier remainder plus this step's release) and books the
+ * exact gain of the stored values, so released - undelivered is the mass the populations
+ * gained from the source.  With FP16/BF16 storage the source rounds stochastically, so the
+ * remainder stays about one step's release; with FP32 it is the rounding residue.  A bubble that
+ * is no longer fed (budgets spent, or its nuclei no longer gas) keeps its remainder undelivered.
+ * Either pointer may be NULL.  Errors: SC_E_INVAL (NULL sim), SC_E_STATE, SC_E_DEVICE. */
+int sc_source_ledger(struct sc_sim* sim, double* released, double* undelivered);
 /* owner[N] (host, caller-owned): the barrier's owner field as of the last test pass; 0 = no
  * bubble, else 1 + the smallest nucleus index of the criterion-merged group that owns the node.
  * All zero when the barrier is off.  Errors: SC_E_INVAL (NULL), SC_E_STATE, SC_E_DEVICE. */
@@ -266,6 +276,10 @@ int sc_lattice(int32_t lattice, int32_t* e /*[q][3]*/, double* w /*[q]*/);
 int sc_get_populations(struct sc_sim* sim, double* f);
 int sc_set_populations(struct sc_sim* sim, const double* f);
 int sc_set_equilibrium(struct sc_sim* sim, const double* rho, const double* u);
+/* The same [q][N] FP64 access to the gas component's populations (two components only,
+ * otherwise SC_E_STATE), so a mixture can be saved and restored whole. */
+int sc_get_gas_populations(struct sc_sim* sim, double* f);
+int sc_set_gas_populations(struct sc_sim* sim, const double* f);
 /* Runs a test pass now, with the merge criterion.  */
 int sc_test_pass(struct sc_sim* sim);
 

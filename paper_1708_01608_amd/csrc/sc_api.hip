@@ -84,7 +84,7 @@ struct sc_sim {
     double tau_v = 1.0;
 
     // nuclei (Sec. 3.1) and agent budgets (Sec. 3)
-    std::vector<double> cen, rad, rem;
+    std::vector<double> cen, rad, rem, budget0;
     double rate = 0.0;
     std::vector<int64_t> nuc_node;
     std::vector<uint32_t> comp;
@@ -96,11 +96,21 @@ struct sc_sim {
     bool have_labels = false;
     int64_t list_count = 0;
 
-    // source schedule: add_host[s * nb + b] for the steps of the current chunk
+    // source schedule: add_host[s * nb + b], the mass bubble b's nuclei release at step s of the
+    // current chunk
     std::vector<double> add_host;
     std::vector<double> rem_host;  // rem after each step of the chunk, [s * n + k]
     std::vector<char> step_active;
     int chunk_len = 0, chunk_pos = 0;
+
+    // source ledger: released agent mass the storage has not taken yet.  On the device per
+    // bubble slot of the last pass (owed, node count, gain, ticket: ledger_nb slots, slot b led
+    // by nucleus ledger_lead[b]); on the host per nucleus for mass whose bubble is not fed
+    DevBuf ledger;
+    int ledger_nb = 0;
+    std::vector<int> ledger_lead;
+    std::vector<double> owed_nuc;
+    uint64_t sr_key = 0;
 
     std::vector<sc_merge_event> events;
     std::vector<sc_topo_event> topo;
@@ -403,9 +413,8 @@ void build_schedule(sc_sim* s, int len)
                     dm += dk;
                     rem[k] -= dk;
                 }
-                const double add = dm / (double)s->bub[b].n;
-                s->add_host[(size_t)st * nb + b] = add;
-                if (add != 0.0) s->step_active[st] = 1;
+                s->add_host[(size_t)st * nb + b] = dm;
+                if (dm != 0.0) s->step_active[st] = 1;
             }
         }
         for (int k = 0; k < n; ++k) s->rem_host[(size_t)st * n + k] = rem[k];
@@ -422,6 +431,49 @@ int upload_schedule(sc_sim* s)
                         s->stream));
     HIPX(hipStreamSynchronize(s->stream));
     return SC_OK;
+}
+
+// Ledger slots of this pass's bubbles: a fed bubble takes over what its nuclei are owed; an
+// unfed one leaves it with them.  Device layout: owed[nb], nodes[nb], gain[nb] (zero),
+// ticket (zero).
+int ledger_setup(sc_sim* s, const std::vector<int32_t>& feed)
+{
+#pragma clang fp contract(off)
+    const int nb = (int)s->bub.size();
+    s->ledger_nb = nb;
+    s->ledger_lead.assign((size_t)nb, -1);
+    if (nb == 0) return SC_OK;
+    std::vector<double> host((size_t)3 * nb + 1, 0.0);
+    for (int b = 0; b < nb; ++b) {
+        s->ledger_lead[b] = s->bub[b].nucleus;
+        host[(size_t)nb + b] = (double)s->bub[b].n;
+        if (!feed[b]) continue;
+        double o = 0.0;
+        for (int k : s->bub_nuclei[b]) {
+            o += s->owed_nuc[k];
+            s->owed_nuc[k] = 0.0;
+        }
+        host[b] = o;
+    }
+    TRY(ensure(s, s->ledger, sizeof(double) * host.size()));
+    HIPX(hipMemcpyAsync(s->ledger.p, host.data(), sizeof(double) * host.size(),
+                        hipMemcpyHostToDevice, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));  // the staging vector lives on the host stack
+    return SC_OK;
+}
+
+SourceLedger ledger_view(sc_sim* s, int step_in_chunk)
+{
+    const int nb = s->ledger_nb;
+    SourceLedger led;
+    led.dm = (const double*)s->add_tab.p + (size_t)step_in_chunk * nb;
+    led.owed = (double*)s->ledger.p;
+    led.nodes = led.owed + nb;
+    led.gain = (unsigned long long*)(led.owed + 2 * (size_t)nb);
+    led.ticket = (unsigned int*)(led.owed + 3 * (size_t)nb);
+    led.nb = nb;
+    led.key = s->sr_key;
+    return led;
 }
 
 int schedule_chunk_len(const sc_sim* s)
@@ -598,7 +650,15 @@ int test_pass(sc_sim* s, bool with_criterion)
         HIPX(hipMemcpyAsync(s->comp.data(), comp_d, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
                             s->stream));
     }
+    // the source ledger of the last pass's bubbles, handed back to the nuclei that led them
+    std::vector<double> owed_back((size_t)s->ledger_nb);
+    if (s->ledger_nb > 0)
+        HIPX(hipMemcpyAsync(owed_back.data(), s->ledger.p, sizeof(double) * owed_back.size(),
+                            hipMemcpyDeviceToHost, s->stream));
     HIPX(hipStreamSynchronize(s->stream));
+    for (size_t b = 0; b < owed_back.size(); ++b)
+        if (owed_back[b] != 0.0) s->owed_nuc[(size_t)s->ledger_lead[b]] += owed_back[b];
+    s->ledger_nb = 0;
     if (s->two) TRY(gas_totals_add(s, tot));
     const bool finite = std::isfinite(tot[0]) && std::isfinite(tot[1]) &&
                         std::isfinite(tot[2]) && std::isfinite(tot[3]);
@@ -703,6 +763,7 @@ int test_pass(sc_sim* s, bool with_criterion)
             HIPX(hipStreamSynchronize(s->stream));
             s->list_count = got;
         }
+        TRY(ledger_setup(s, feed));
     }
 
     // topological merges: nuclei of one component join one group (smallest index leads)
@@ -1053,6 +1114,10 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
     s->cen.assign((size_t)3 * n, 0.0);
     s->rad.assign((size_t)n, 0.0);
     s->rem.assign((size_t)n, 0.0);
+    s->budget0.assign((size_t)n, 0.0);
+    s->owed_nuc.assign((size_t)n, 0.0);
+    s->ledger_nb = 0;
+    s->sr_key = s->p.noise_seed ^ 0x736f757263652d31ull;  // stochastic rounding of the source
     s->nuc_node.assign((size_t)n, 0);
     s->merge_parent.resize((size_t)n);
     s->topo_parent.resize((size_t)n);
@@ -1062,6 +1127,7 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
         if (s->d == 2) s->cen[3 * k + 2] = 0.0;
         s->rad[k] = radius[k];
         s->rem[k] = budget[k];
+        s->budget0[k] = budget[k];
         s->nuc_node[k] = nearest_node(s, &s->cen[3 * k]);
         s->merge_parent[k] = k;
         s->topo_parent[k] = k;
@@ -1111,11 +1177,11 @@ int sc_step(sc_sim* s, int32_t nsteps)
         if (s->step_active.size() && s->step_active[s->chunk_pos] && s->list_count > 0) {
             TRY(prof_begin(s, SC_KERNEL_SOURCE, &pe));
             // the agent's gas goes to the gas component when there is one
+            if (s->ledger_nb != nb) return fail(SC_E_STATE, "source ledger out of step");
             HIPX(launch_source(s->q, s->p.storage, s->two ? s->fv[s->cur] : s->f[s->cur],
                                (const uint32_t*)s->list_node.p,
                                (const int32_t*)s->list_slot.p, s->list_count,
-                               (const double*)s->add_tab.p + (size_t)s->chunk_pos * nb, fa,
-                               s->stream));
+                               ledger_view(s, s->chunk_pos), s->t, fa, s->stream));
             TRY(prof_end(s, pe));
         }
         if (!s->rem.empty() && s->chunk_len > 0) {
@@ -1453,6 +1519,30 @@ int sc_nuclei(sc_sim* s, uint32_t* comp, double* remaining)
     return SC_OK;
 }
 
+int sc_source_ledger(sc_sim* s, double* released, double* undelivered)
+{
+#pragma clang fp contract(off)
+    TRY(check_usable(s));
+    if (released) {
+        double r = 0.0;
+        for (size_t k = 0; k < s->rem.size(); ++k) r += s->budget0[k] - s->rem[k];
+        *released = r;
+    }
+    if (undelivered) {
+        double o = 0.0;
+        for (double v : s->owed_nuc) o += v;
+        if (s->ledger_nb > 0) {
+            std::vector<double> owed((size_t)s->ledger_nb);
+            HIPX(hipMemcpyAsync(owed.data(), s->ledger.p, sizeof(double) * owed.size(),
+                                hipMemcpyDeviceToHost, s->stream));
+            HIPX(hipStreamSynchronize(s->stream));
+            for (double v : owed) o += v;
+        }
+        *undelivered = o;
+    }
+    return SC_OK;
+}
+
 int sc_time(sc_sim* s, int64_t* step)
 {
     if (!s || !step) return fail(SC_E_INVAL, "NULL argument");
@@ -1505,6 +1595,35 @@ int sc_set_populations(sc_sim* s, const double* f)
     HIPX(hipMemcpyAsync(s->tmp64.p, f, bytes, hipMemcpyHostToDevice, s->stream));
     HIPX(launch_set_f(s->q, s->p.storage, s->f[s->cur], (const double*)s->tmp64.p,
                       init_args(s, 0.0), s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+// The gas component's populations, [q][N] FP64 as for the liquid (checkpoints of the mixture).
+int sc_get_gas_populations(sc_sim* s, double* f)
+{
+    TRY(check_usable(s));
+    if (!s->two) return fail(SC_E_STATE, "no gas component (components = 1)");
+    if (!f) return fail(SC_E_INVAL, "NULL output");
+    const size_t bytes = sizeof(double) * (size_t)s->q * (size_t)s->N;
+    TRY(ensure(s, s->tmp64, bytes));
+    HIPX(launch_get_f(s->q, s->p.storage, s->fv[s->cur], (double*)s->tmp64.p,
+                      init_args_gas(s, 0.0), s->stream));
+    HIPX(hipMemcpyAsync(f, s->tmp64.p, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    return SC_OK;
+}
+
+int sc_set_gas_populations(sc_sim* s, const double* f)
+{
+    TRY(check_usable(s));
+    if (!s->two) return fail(SC_E_STATE, "no gas component (components = 1)");
+    if (!f) return fail(SC_E_INVAL, "NULL input");
+    const size_t bytes = sizeof(double) * (size_t)s->q * (size_t)s->N;
+    TRY(ensure(s, s->tmp64, bytes));
+    HIPX(hipMemcpyAsync(s->tmp64.p, f, bytes, hipMemcpyHostToDevice, s->stream));
+    HIPX(launch_set_f(s->q, s->p.storage, s->fv[s->cur], (const double*)s->tmp64.p,
+                      init_args_gas(s, 0.0), s->stream));
     HIPX(hipStreamSynchronize(s->stream));
     return SC_OK;
 }

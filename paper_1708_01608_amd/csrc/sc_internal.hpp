@@ -178,10 +178,21 @@ struct FilmOut {
 hipError_t launch_film(int q, int storage, const void* f, const uint32_t* labels,
                        const FilmArgs& g, FilmOut* out_d, const FieldArgs& a, hipStream_t st);
 
-// Blowing-agent source for one step: f_i(x) += w_i * add[slot] on the listed gas nodes.
+// Blowing-agent source for one step: f_i(x) += w_i * T_b / n_b on the listed gas nodes, with
+// T_b = owed[b] + dm[b]; the stored values' exact gain closes the ledger (owed[b] = T_b - gain).
+// Device tables of nb bubble slots; gain (2^-40 fixed point) and ticket are zero between steps.
+struct SourceLedger {
+    const double* dm;          // this step's release of each bubble's nuclei
+    const double* nodes;       // n_b, gas nodes listed for the bubble
+    double* owed;              // mass released earlier that the storage has not taken yet
+    unsigned long long* gain;  // sum of this step's gains in 2^-40 units (two's complement)
+    unsigned int* ticket;      // blocks finished in this launch
+    int nb;
+    uint64_t key;              // stochastic-rounding stream (16-bit storage)
+};
 hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
-                         const int32_t* list_slot, int64_t count, const double* add_d,
-                         const FieldArgs& a, hipStream_t st);
+                         const int32_t* list_slot, int64_t count, const SourceLedger& led,
+                         int64_t t, const FieldArgs& a, hipStream_t st);
 
 // Barrier owner field: seed = owner id of each gas node's bubble (ids_d[slot], 0 elsewhere;
 // nb == 0 writes zeros and reads neither table), then one corona layer per grow call.

@@ -523,24 +523,90 @@ __global__ void k_merge(const S* f, const uint32_t* labels, const MergePair* pai
 }
 
 // ---- blowing-agent source (Sec. 3): f_i(x) += w_i dm_b / n_b on the gas nodes of bubble b ----
+// Each step bubble b is owed T_b = owed_b + dm_b: what earlier steps could not place plus this
+// step's release.  Every listed node adds w_i T_b / n_b to its populations and rounds the sum
+// into the storage type: to nearest for FP32, stochastically for FP16/BF16, whose spacing at a
+// gas node (~5e-4 at -0.59 in FP16) exceeds the per-step increment (~1e-7) by orders of
+// magnitude, so rounding to nearest would drop every increment.  The exact gain of the stored
+// values (FP64 differences) is summed per bubble in fixed point (2^-40 units, integer atomics,
+// so the sum does not depend on the order of the nodes), and the last block to finish sets
+// owed_b = T_b - gain_b: the ledger carries what the storage could not take into the next step.
+
+// The storage value next to the 16-bit pattern b toward +inf (up) or -inf: sign-magnitude
+// layout, so moving away from zero adds one to the magnitude; +-0 steps to +-the smallest
+// subnormal.
+__device__ __forceinline__ uint16_t next_bits16(uint16_t b, bool up)
+{
+    const bool neg = (b & 0x8000u) != 0;
+    if ((b & 0x7fffu) == 0) return up ? 0x0001u : 0x8001u;
+    return (up != neg) ? (uint16_t)(b + 1u) : (uint16_t)(b - 1u);
+}
+
+// v rounded into the storage type.  FP32: to nearest.  FP16 / BF16: stochastically, to one of
+// the two storage values lo <= v <= hi, hi with probability (v - lo) / (hi - lo), u in [0, 1),
+// so the expected stored value is v.  (S)(float)v is one of lo, hi even where rounding twice
+// picks the farther one; which of them it is follows from comparing it with v.
+template <typename S>
+__device__ __forceinline__ S round_into(double v, double u)
+{
+    const S h = static_cast<S>(static_cast<float>(v));
+    const double hd = (double)static_cast<float>(h);
+    if (hd == v) return h;
+    const bool below = hd < v;
+    const S o = __builtin_bit_cast(S, next_bits16(__builtin_bit_cast(uint16_t, h), below));
+    const double od = (double)static_cast<float>(o);
+    const double lo = below ? hd : od, hi = below ? od : hd;
+    const bool take_hi = u < (v - lo) / (hi - lo);
+    return take_hi ? (below ? o : h) : (below ? h : o);
+}
+template <>
+__device__ __forceinline__ float round_into<float>(double v, double) { return (float)v; }
+
+constexpr double kGainUnit = 1.0 / 1099511627776.0;  // 2^-40
+constexpr double kGainScale = 1099511627776.0;
+
 template <int Q, typename S>
 __global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_slot, int64_t count,
-                         const double* add, FieldArgs a)
+                         SourceLedger led, int64_t t, FieldArgs a)
 {
     using L = lat<Q>;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const double ab = add[list_slot[k]];
-        if (ab == 0.0) continue;
+        const int b = list_slot[k];
+        const double T = led.owed[b] + led.dm[b];
+        if (T == 0.0) continue;
+        const double ab = T / led.nodes[b];
         const int64_t n = list_node[k];
         int x, y, z;
         coords3(n, a.nx, a.ny, x, y, z);
+        double gain = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             S* slot = f + (int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a);
-            *slot = store_f<S>(load_f(*slot) + (float)(L::wd[i] * ab));
+            const S old = *slot;
+            const double oldd = (double)load_f(old);
+            const double u = unit_noise(led.key, ((uint64_t)t * (uint64_t)a.N + (uint64_t)n) *
+                                                     (uint64_t)Q + (uint64_t)i);
+            const S nw = round_into<S>(oldd + L::wd[i] * ab, u);
+            *slot = nw;
+            gain += (double)load_f(nw) - oldd;
         }
+        atomicAdd(&led.gain[b], (unsigned long long)(long long)rint(gain * kGainScale));
     }
+    // the last block to finish closes the ledger of this step
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(led.ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int b = threadIdx.x; b < led.nb; b += blockDim.x) {
+        const long long g = (long long)atomicExch(&led.gain[b], 0ull);
+        const double T = led.owed[b] + led.dm[b];
+        led.owed[b] = T - (double)g * kGainUnit;
+    }
+    if (threadIdx.x == 0) *led.ticket = 0u;
 }
 
 // ---- film geometry of a bubble pair (Sec. 3 film disc; Fig. 3) --------------------------------
@@ -866,13 +932,13 @@ hipError_t launch_merge(int q, int storage, const void* f, const uint32_t* label
 }
 
 hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
-                         const int32_t* list_slot, int64_t count, const double* add_d,
-                         const FieldArgs& a, hipStream_t st)
+                         const int32_t* list_slot, int64_t count, const SourceLedger& led,
+                         int64_t t, const FieldArgs& a, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     SC_DISPATCH(q, storage,
                 hipLaunchKernelGGL((k_source<QQ, SS>), grid_for(count), dim3(256), 0, st, (SS*)f,
-                                   list_node, list_slot, count, add_d, a));
+                                   list_node, list_slot, count, led, t, a));
     return hipGetLastError();
 }
 

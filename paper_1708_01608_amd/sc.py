@@ -100,9 +100,10 @@ EXPORTS = (
     "sc_seed_nuclei", "sc_step", "sc_fields", "sc_fields_device", "sc_laplacian_p",
     "sc_laplacian_p_device", "sc_label_bubbles",
     "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei",
-    "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density",
+    "sc_source_ledger", "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density",
     "sc_set_gas_equilibrium", "sc_time",
     "sc_lattice", "sc_get_populations", "sc_set_populations", "sc_set_equilibrium",
+    "sc_get_gas_populations", "sc_set_gas_populations",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
     "sc_hbm_probe", "sc_batch_tune",
@@ -144,6 +145,9 @@ def load_library(path=LIB_PATH):
         "sc_bubbles": (C.c_int, [P, P, C.c_int32, P]),
         "sc_last_labels": (C.c_int, [P, P]),
         "sc_nuclei": (C.c_int, [P, P, P]),
+        "sc_source_ledger": (C.c_int, [P, P, P]),
+        "sc_get_gas_populations": (C.c_int, [P, P]),
+        "sc_set_gas_populations": (C.c_int, [P, P]),
         "sc_owner": (C.c_int, [P, P]),
         "sc_buoyancy_density": (C.c_int, [P, P]),
         "sc_film_geometry": (C.c_int, [P, C.c_int32, C.c_int32, P, P, P]),
@@ -477,6 +481,22 @@ class Sim:
         rem = np.zeros(max(n, 1))
         _check(self._lib.sc_nuclei(self._h, _ptr(comp), _ptr(rem)))
         return comp[:n], rem[:n]
+
+    def source_ledger(self):
+        """(released, undelivered): agent mass the nuclei have given up, and the part of it the
+        populations have not taken yet (FP64)."""
+        rel, und = C.c_double(), C.c_double()
+        _check(self._lib.sc_source_ledger(self._h, C.byref(rel), C.byref(und)))
+        return rel.value, und.value
+
+    def get_gas_populations(self):
+        f = np.zeros((self.q, self.N))
+        _check(self._lib.sc_get_gas_populations(self._h, _ptr(f)))
+        return f
+
+    def set_gas_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.q, self.N)
+        _check(self._lib.sc_set_gas_populations(self._h, _ptr(f)))
 
     def get_populations(self):
         f = np.zeros((self.q, self.N))

@@ -225,6 +225,20 @@ int sc_laplacian_p_device(struct sc_sim* sim, double* p_dev, double* lap_dev);
  * Errors: SC_E_INVAL (NULL sim or labels), SC_E_STATE, SC_E_DEVICE. */
 int sc_label_bubbles(struct sc_sim* sim, const uint8_t* mask, uint32_t* labels, int64_t* ncomp);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): sc_label_bubbles on device memory with no allocation.
+ * mask_dev: N bytes of the sim's device (nonzero = gas) or NULL for rho < gas_threshold on the
+ * current state; labels_dev: N uint32 of the sim's device, written with the same canonical labels
+ * as sc_label_bubbles; *ncomp (host, may be NULL) the component count.  The union-find parents and
+ * the counter live in a static device array of 16,777,216 + 64 uint32 (64 MiB) that each GPU the
+ * library runs on holds until the process ends; a box of more than 16,777,216 nodes is SC_E_INVAL.
+ * Every call on one GPU shares that array, so calls that overlap in time on one GPU (from two host
+ * threads, or on two streams) race; calls in sequence are independent.  Buffers that are not
+ * memory of the sim's device, or too small, are SC_E_INVAL before any kernel runs.  Returns after
+ * the sim's stream has finished the work.  Errors: SC_E_INVAL, SC_E_STATE, SC_E_DEVICE. */
+int sc_label_bubbles_noalloc(struct sc_sim* sim, const uint8_t* mask_dev, uint32_t* labels_dev,
+                             int64_t* ncomp);
+
 /* Registry of the last test pass and of all passes so far.  *n_total receives the full count;
  * at most cap entries are copied. */
 int sc_merge_events(struct sc_sim* sim, sc_merge_event* out, int32_t cap, int32_t* n_total);

@@ -1342,6 +1342,77 @@ int sc_label_bubbles(sc_sim* s, const uint8_t* mask, uint32_t* labels, int64_t* 
     return SC_OK;
 }
 
+// ---- allocation-free labelling -----------------------------------------------------------------
+// The union-find parent array and the component counter of sc_label_bubbles_noalloc live in a
+// file-scope device array: every GPU the library runs on holds its own copy from the time the
+// code object is loaded until the process ends.  Host code never passes `scratch` itself (in host
+// code the name is a stand-in, not a device address): its device address is looked up once per
+// device and kept in scratch_dev.
+constexpr int64_t kScratchMaxNodes = 16777216;  // 256^3 nodes: 64 MiB of parents
+constexpr int64_t kScratchWords = kScratchMaxNodes + 64;
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+uint32_t* scratch_dev[kMaxDevices] = {};
+
+int scratch_of_current_device(uint32_t** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SC_E_DEVICE, "hipGetDevice failed");
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(SC_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(SC_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                         hipGetErrorString(e));
+        }
+        scratch_dev[dev] = (uint32_t*)p;
+    }
+    *out = scratch_dev[dev];
+    return SC_OK;
+}
+}  // namespace
+
+int sc_label_bubbles_noalloc(sc_sim* s, const uint8_t* mask_dev, uint32_t* labels_dev,
+                             int64_t* ncomp)
+{
+    TRY(check_usable(s));
+    if (!labels_dev) return fail(SC_E_INVAL, "NULL labels");
+    if (s->N > kScratchMaxNodes)
+        return fail(SC_E_INVAL, "box of " + std::to_string(s->N) + " nodes exceeds the " +
+                                    std::to_string(kScratchMaxNodes) +
+                                    "-node scratch of the allocation-free labelling");
+    TRY(check_device_buffer(labels_dev, sizeof(uint32_t) * (size_t)s->N, "labels"));
+    if (mask_dev) TRY(check_device_buffer(mask_dev, (size_t)s->N, "mask"));
+    uint32_t* base = nullptr;
+    TRY(scratch_of_current_device(&base));
+    uint32_t* parent = base;
+    uint32_t* ncomp_d = base + kScratchMaxNodes;  // 256-byte aligned: kScratchMaxNodes * 4
+    const FieldArgs fa = field_args(s);
+    // every parent entry below N is written by the mask kernel; the counter is cleared by a
+    // kernel (the array keeps the previous call's contents)
+    if (mask_dev)
+        HIPX(launch_mask_from_bytes(mask_dev, parent, s->N, s->stream));
+    else
+        HIPX(launch_mask_from_rho(s->q, s->p.storage, s->f[s->cur], parent, fa, s->stream));
+    HIPX(launch_union(s->q, parent, fa, s->stream));
+    HIPX(launch_fill_i32((int32_t*)ncomp_d, 0, 1, s->stream));
+    HIPX(launch_flatten(parent, labels_dev, ncomp_d, s->N, s->stream));
+    uint32_t nc = 0;
+    HIPX(hipMemcpyAsync(&nc, ncomp_d, sizeof(nc), hipMemcpyDeviceToHost, s->stream));
+    HIPX(hipStreamSynchronize(s->stream));
+    if (ncomp) *ncomp = nc;
+    return SC_OK;
+}
+
 int sc_merge_events(sc_sim* s, sc_merge_event* out, int32_t cap, int32_t* n_total)
 {
     if (!s) return fail(SC_E_INVAL, "NULL simulation handle");

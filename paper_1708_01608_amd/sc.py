@@ -98,7 +98,7 @@ class BatchResult(C.Structure):
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
     "sc_seed_nuclei", "sc_step", "sc_fields", "sc_fields_device", "sc_laplacian_p",
-    "sc_laplacian_p_device", "sc_label_bubbles",
+    "sc_laplacian_p_device", "sc_label_bubbles", "sc_label_bubbles_noalloc",
     "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei",
     "sc_source_ledger", "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density",
     "sc_set_gas_equilibrium", "sc_time",
@@ -145,6 +145,7 @@ def load_library(path=LIB_PATH):
         "sc_bubbles": (C.c_int, [P, P, C.c_int32, P]),
         "sc_last_labels": (C.c_int, [P, P]),
         "sc_nuclei": (C.c_int, [P, P, P]),
+        "sc_label_bubbles_noalloc": (C.c_int, [P, P, P, P]),
         "sc_source_ledger": (C.c_int, [P, P, P]),
         "sc_get_gas_populations": (C.c_int, [P, P]),
         "sc_set_gas_populations": (C.c_int, [P, P]),

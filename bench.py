@@ -11,7 +11,11 @@ hot path.  Inputs (the populations) are resident in HBM before timing starts.
 Prints one JSON line.  `value` is MLUPS (million lattice-node updates per second) of the whole
 job; `roofline` is the step kernel's algorithmic bytes per launch over its HIP-event-measured
 average duration on the simulation stream, against the 8 TB/s HBM peak; `cpu_baseline` is the
-FP64 CPU oracle timed on a bounded sample of the same workload on this host.
+FP64 CPU oracle timed on a bounded sample of the same workload on this host.  With the default
+workload the same line also carries the two system patterns: `precision` (the 512^3 foam with
+FP32, FP16 and BF16 storage, and each storage type's error against the FP64 oracle on a
+two-phase box) and `batching` (the 4096-box batch in one persistent launch against the same kind
+of boxes run one at a time).
 """
 import argparse
 import hashlib
@@ -47,7 +51,12 @@ def parse():
                          "stored by paper_1708_01608_amd.tune, else the built-in default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=0,
-                    help="oracle steps timed for cpu_baseline (0: pick ~10-30 s)")
+                    help="oracle steps timed for cpu_baseline after 10 untimed ones (0: 100, or "
+                         "fewer where 100 would take over a minute)")
+    ap.add_argument("--no-patterns", action="store_true",
+                    help="default workload only: leave out the precision and batching keys")
+    ap.add_argument("--precision-steps", type=int, default=4,
+                    help="bench steps (K lattice steps each) timed per storage type at 512^3")
     ap.add_argument("--variants", action="store_true",
                     help="also time FP32-compute / 16-bit storage variants (extra JSON lines)")
     ap.add_argument("--batch-sample", type=int, default=32, metavar="N",
@@ -154,25 +163,52 @@ def run_gpu(spec, args, storage, compute, steps, warmup, tile=None):
                 test_ms=test_ms, test_n=test_n, tile=tile_used, compute=comp)
 
 
-def cpu_baseline(spec, sample_steps):
+def cpu_baseline_leg(spec, sample_steps, err_spec=None, err_steps=0, err_fields=None):
+    """The FP64 CPU oracle on this host (the only part of the benchmark that runs it).
+
+    (1) Its speed on a sample of the workload: 10 untimed steps, then `sample_steps` timed ones
+    (100 unless that would take over a minute), test passes off.  (2) With err_fields, the FP64
+    reference of the precision error box at err_steps, against which the GPU fields of each
+    storage type (err_fields[(storage, compute)] = (rho, u)) are stated: rho as the maximum
+    pointwise relative error, u as the maximum error over max |u| (u passes through zero)."""
+    import numpy as np
+
     from oracle import OracleSim, num_threads
 
     o = OracleSim(spec.q, spec.nx, spec.ny, spec.nz, spec.tau, spec.G, spec.rho_l, spec.rho_g,
                   spec.amp, spec.seed, spec.theta, 0, spec.film_max,
                   two_component=spec.two_component)
     o.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
+    warm = 10
+    t0 = time.perf_counter()
+    o.step(warm)
+    per_step = (time.perf_counter() - t0) / warm
     if sample_steps <= 0:
-        t0 = time.perf_counter()
-        o.step(1)
-        one = time.perf_counter() - t0
-        sample_steps = int(max(1, min(2000, 15.0 / max(one, 1e-6))))
+        sample_steps = int(max(10, min(100, 60.0 / max(per_step, 1e-6))))
     t0 = time.perf_counter()
     o.step(sample_steps)
     dt = time.perf_counter() - t0
-    return dict(value=round(spec.N * sample_steps / dt / 1e6, 3), unit="MLUPS",
+    base = dict(value=round(spec.N * sample_steps / dt / 1e6, 3), unit="MLUPS",
                 cores=num_threads(), kind="oracle",
                 sample=f"{spec.name} {spec.nx}x{spec.ny}x{spec.nz}, {sample_steps} oracle steps "
-                       f"(FP64 collide-stream + source; test passes off), {dt:.1f} s")
+                       f"after {warm} untimed (FP64 collide-stream + source; test passes off), "
+                       f"{dt:.1f} s")
+    del o
+    errors = None
+    if err_fields:
+        e = OracleSim(err_spec.q, err_spec.nx, err_spec.ny, err_spec.nz, err_spec.tau,
+                      err_spec.G, err_spec.rho_l, err_spec.rho_g, err_spec.amp, err_spec.seed,
+                      err_spec.theta, err_spec.K, err_spec.film_max)
+        e.seed_nuclei(err_spec.centres, err_spec.radii, err_spec.budgets, err_spec.rate)
+        e.step(err_steps)
+        ro, uo, _ = e.fields()
+        umax = float(np.max(np.abs(uo)))
+        errors = {}
+        for (storage, compute), (rg, ug) in err_fields.items():
+            errors[f"{storage} storage / {compute} compute"] = {
+                "rho": float(f"{np.max(np.abs(rg - ro) / ro):.3e}"),
+                "u": float(f"{np.max(np.abs(ug - uo)) / umax:.3e}")}
+    return base, errors
 
 
 def copy_probe(nbytes):
@@ -192,40 +228,39 @@ def copy_probe(nbytes):
                       "copy_GBps": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
 
 
-def run_batch(args):
-    """The batching pattern: every box of the batch workload in one persistent launch; one bench
-    step = the whole job (every box to its merge, topological merge or max_steps)."""
+def batch_measure(compute, runs, warmup, sample):
+    """The batching pattern: every box of the 4096-box workload in one persistent launch (one
+    run = the whole job, every box to its merge, topological merge or max_steps), then `sample`
+    of the same boxes one at a time through sc_create/sc_step for comparison."""
     import torch
 
     from paper_1708_01608_amd import sc
     from paper_1708_01608_amd import workloads as W
 
     spec = W.batch()
-    compute = "f64" if args.compute == "auto" else args.compute
     b = sc.Batch(spec, compute=compute)
     rows_per_thread, tune_ms = b.tune(trial_steps=50)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kms = 0.0
-    for _ in range(args.steps):
+    for _ in range(runs):
         res, ms = b.run()
         kms += ms
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     node_steps = sum(int(spec.nx[k]) * int(spec.ny[k]) * res[k]["steps_run"] for k in range(spec.n))
-    mlups = node_steps * args.steps / wall / 1e6
-    achieved = 72.0 * node_steps / (kms / args.steps / 1e3) / 1e9
+    mlups = node_steps * runs / wall / 1e6
+    achieved = 72.0 * node_steps / (kms / runs / 1e3) / 1e9
     merged = sum(1 for r in res if r["merge_step"] >= 0)
     topo = sum(1 for r in res if r["topo_step"] >= 0 and r["merge_step"] < 0)
     b.close()
-    # the same kind of boxes one at a time through the single-box API (sampled)
-    ns = max(0, min(args.batch_sample, spec.n))
-    sample = list(range(0, spec.n, max(1, spec.n // max(ns, 1))))[:ns]
+    ns = max(0, min(sample, spec.n))
+    picks = list(range(0, spec.n, max(1, spec.n // max(ns, 1))))[:ns]
     t1 = time.perf_counter()
     ns1 = 0
-    for k in sample:
+    for k in picks:
         s = spec.instance(k)
         g = sc.Sim.from_spec(s, compute=compute)
         g.seed_nuclei(s.centres, s.radii, s.budgets, 0.0)
@@ -233,38 +268,87 @@ def run_batch(args):
             g.step(spec.K)
         ns1 += s.N * g.t
         g.close()
-    one_by_one = ns1 / (time.perf_counter() - t1) / 1e6 if sample else None
+    one_by_one = ns1 / (time.perf_counter() - t1) / 1e6 if picks else None
+    return dict(spec=spec, mlups=mlups, wall=wall, kms=kms, achieved=achieved,
+                node_steps=node_steps, merged=merged, topo=topo,
+                rows_per_thread=rows_per_thread, tune_ms=tune_ms, one_by_one=one_by_one,
+                sample=len(picks))
+
+
+def run_batch(args):
+    """--workload batch: the batching pattern as the benchmark's own line."""
+    compute = "f64" if args.compute == "auto" else args.compute
+    m = batch_measure(compute, args.steps, args.warmup, args.batch_sample)
+    spec = m["spec"]
     out = {
         "metric": "Shan-Chen MLUPS & % of HBM roofline",
-        "value": round(mlups, 1),
+        "value": round(m["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "ms_per_step": round(m["wall"] * 1e3 / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": compute,
         "data": "synthetic",
         "config": {"workload": "batch", "lattice": "D2Q9", "boxes": spec.n,
-                   "nodes": int((spec.nx * spec.ny).sum()), "node_steps": node_steps,
+                   "nodes": int((spec.nx * spec.ny).sum()), "node_steps": m["node_steps"],
                    "max_steps": spec.max_steps, "test_every": spec.K, "storage": "f32",
-                   "compute": compute, "rows_per_thread": rows_per_thread,
-                   "tune_ms_rb124": [round(v, 2) for v in tune_ms],
-                   "merged_by_criterion": merged,
-                   "merged_topologically_first": topo},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": batch_traffic_from_profile(compute, rows_per_thread, node_steps),
+                   "compute": compute, "rows_per_thread": m["rows_per_thread"],
+                   "tune_ms_rb124": [round(v, 2) for v in m["tune_ms"]],
+                   "merged_by_criterion": m["merged"],
+                   "merged_topologically_first": m["topo"]},
+        "roofline": {"bound": "hbm", "achieved": round(m["achieved"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(m["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": batch_traffic_from_profile(compute, m["rows_per_thread"],
+                                                           m["node_steps"]),
                      "kernel": "k_batch", "bytes_per_node_step": 72,
-                     "kernel_ms": round(kms / args.steps, 3)},
-        "one_by_one_MLUPS": round(one_by_one, 1) if one_by_one is not None else None,
-        "one_by_one_sample": f"{len(sample)} boxes through sc_create/sc_step",
+                     "kernel_ms": round(m["kms"] / args.steps, 3)},
+        "one_by_one_MLUPS": round(m["one_by_one"], 1) if m["one_by_one"] is not None else None,
+        "one_by_one_sample": f"{m['sample']} boxes through sc_create/sc_step",
     }
     print(json.dumps(out), flush=True)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+
+
+def precision_measure(args):
+    """The precision pattern on the 512^3 foam (D3Q19, 400 nuclei, tau 0.9, K 50): the step kernel
+    with FP32 storage (FP64 and FP32 arithmetic) against FP16 and BF16 shifted storage (FP32
+    arithmetic), each timed over `precision_steps` bench steps after one untimed."""
+    spec = workload_spec("foam_3d_large")
+    rows = {}
+    for storage, compute in (("f32", "f64"), ("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
+        r = run_gpu(spec, args, storage, compute, args.precision_steps, 1)
+        b = bytes_per_node(spec.q, storage) * spec.N
+        avg_s = r["step_ms"] / 1e3 / max(r["launches"], 1)
+        rows[f"{storage} storage / {compute} compute"] = {
+            "MLUPS": round(spec.N * args.precision_steps * spec.K / r["wall"] / 1e6, 1),
+            "stencil_only_MLUPS": round(spec.N / avg_s / 1e6, 1),
+            "bytes_per_node": bytes_per_node(spec.q, storage),
+            "avg_launch_us": round(avg_s * 1e6, 1),
+            "achieved_GBps": round(b / avg_s / 1e9, 1),
+            "frac": round(b / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+    return spec, rows
+
+
+def error_box_fields(steps):
+    """GPU fields of the precision error box after `steps` steps, per storage type."""
+    from paper_1708_01608_amd import sc
+    from paper_1708_01608_amd import workloads as W
+
+    spec = W.precision_error_box()
+    fields = {}
+    for storage, compute in (("f32", "f64"), ("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
+        g = sc.Sim.from_spec(spec, storage=storage, compute=compute)
+        g.seed_nuclei(spec.centres, spec.radii, spec.budgets, spec.rate)
+        g.step(steps)
+        rho, u, _ = g.fields()
+        g.close()
+        fields[(storage, compute)] = (rho.astype("float64"), u.astype("float64"))
+    return spec, fields
 
 
 def main():
@@ -360,8 +444,44 @@ def main():
     out["roofline"]["measured_copy_GBps"] = round(copy_gbs, 1)
     out["roofline"]["measured_read_GBps"] = round(read_gbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
+    patterns = (args.workload == "foam_3d" and not args.no_patterns and not args.barrier and
+                not args.gravity and args.tile is None and args.storage == "f32")
+    err_spec = err_fields = None
+    err_steps = 100
+    if patterns:
+        pspec, rows = precision_measure(args)
+        err_spec, err_fields = error_box_fields(err_steps)
+        base = rows["f32 storage / f64 compute"]["MLUPS"]
+        out["precision"] = {
+            "workload": f"{pspec.name} {pspec.nx}^3 D3Q19, {len(pspec.radii)} nuclei, tau "
+                        f"{pspec.tau}, K {pspec.K}; 16-bit storage holds f_i - w_i rho_l",
+            "runs": rows,
+            "f16_vs_f32_storage_MLUPS": round(rows["f16 storage / f32 compute"]["MLUPS"] / base, 3),
+            "bf16_vs_f32_storage_MLUPS": round(rows["bf16 storage / f32 compute"]["MLUPS"] / base,
+                                               3),
+            "error_vs_fp64": None,
+            "error_box": f"{err_spec.name}: two spheres R {err_spec.radii[0]:g}, "
+                         f"{err_spec.nx}x{err_spec.ny}x{err_spec.nz}, tau {err_spec.tau}, "
+                         f"rho_l {err_spec.rho_l}, after {err_steps} steps (both spheres persist)",
+        }
+        bm = batch_measure("f64", 1, 1, args.batch_sample)
+        out["batching"] = {
+            "workload": f"batch: {bm['spec'].n} D2Q9 two-bubble boxes 64..256 per side, "
+                        f"to the merge or {bm['spec'].max_steps} steps, one persistent launch",
+            "MLUPS": round(bm["mlups"], 1),
+            "job_s": round(bm["wall"], 3),
+            "frac": round(bm["achieved"] / HBM_PEAK_GBS, 4),
+            "one_by_one_MLUPS": (round(bm["one_by_one"], 1) if bm["one_by_one"] is not None
+                                 else None),
+            "one_by_one_sample": f"{bm['sample']} boxes through sc_create/sc_step",
+            "batched_vs_one_by_one": (round(bm["mlups"] / bm["one_by_one"], 1)
+                                      if bm["one_by_one"] else None),
+        }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample_steps)
+        out["cpu_baseline"], errors = cpu_baseline_leg(spec, args.cpu_sample_steps, err_spec,
+                                                       err_steps, err_fields)
+        if patterns:
+            out["precision"]["error_vs_fp64"] = errors
     print(json.dumps(out), flush=True)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)

@@ -183,6 +183,20 @@ def foam_3d_error_run(seed=4, steps=2000):
     return foam_3d_large(n=128, n_nuclei=max(1, round(400 / 64)), seed=seed, steps=steps)
 
 
+def precision_error_box(seed=4, steps=2000, radius=12.0, gap=14, rho_l=1.80):
+    """Two-phase error box of the precision workload (D3Q19, tau 0.9, G -5, K 50): two spheres of
+    radius 12, 14 liquid nodes apart on the x axis of a 94 x 56 x 56 box.  At rho_l = 1.93 (the
+    flat-interface coexistence density) a sphere's Laplace pressure condenses its gas, as it does
+    the foam's radius-3 nuclei; a slightly stretched liquid at 1.80 keeps both spheres (about
+    10,300 gas nodes each at t = 1000), so errors are stated on a box that holds gas."""
+    nx, ny = int(4 * radius + gap + 32), int(2 * radius + 32)
+    c = pair_centres(nx, ny, radius, gap)
+    c[:, 2] = ny / 2.0 - 0.5
+    return SimSpec(name="precision_error_box", q=19, nx=nx, ny=ny, nz=ny, tau=0.9, G=-5.0,
+                   rho_l=rho_l, rho_g=0.16, amp=1e-3, seed=seed, K=50, steps=steps, centres=c,
+                   radii=np.array([radius, radius]), budgets=np.zeros(2), rate=0.0)
+
+
 # The mixture's parameters: cross repulsion G_cross, gas relaxation time (<= 0: the liquid's),
 # gas density in the nuclei and dissolved in the liquid; the liquid component is 1.0 in the
 # liquid and 0.05 in the nuclei.

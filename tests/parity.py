@@ -4,25 +4,37 @@ import numpy as np
 from oracle import OracleSim
 from paper_1708_01608_amd import sc
 
-# Tolerances against the FP64 oracle over 100-step horizons.
+# Errors against the FP64 oracle over 100-step horizons.
 # rho: max pointwise relative error; u: max error over max |u| (u passes through zero).
-# FP32 storage with FP64 arithmetic: the 1e-5 bar.  FP32 arithmetic: steady nodes repeat the
-# same FP32 roundings every step, so the error grows about linearly, ~100 steps x a few ulp
-# (6e-8) x the amplification of the interface dynamics; measured up to 1.7e-4 (rho) and 8e-5
-# (u) on the boxes below, gated at 3e-4 / 1e-3.
-# 16-bit storage of f_i - w_i rho_liquid: gas populations sit ~1.77 w_i away from the shift, so
-# one rounding is ~2^-12 (FP16) or 2^-9 (BF16) of ~0.8, i.e. ~1e-3 / 8e-3 of the gas density, and
-# u = j / rho divides by rho_gas = 0.16.  Measured on the two-bubble box at t = 100: FP16 rho
-# 5.6e-3, u 0.37 max|u|; BF16 rho 7.0e-2, u 1.37 max|u|.  These are reported values, gated only
-# against regression (about twice the measurement), not a precision claim.
+#
+# Gated: FP32 storage with FP64 arithmetic, at the 1e-5 bar.
+#
+# Reported, not gated: FP32 arithmetic, FP16 and BF16 storage.  Their errors are printed by the
+# tests and stated beside their speed; the bounds in SANITY only reject a broken kernel (a wrong
+# sign, index or storage shift blows the fields up to O(1) relative error and beyond), they make
+# no precision claim.  For scale: FP32 arithmetic measured up to 1.7e-4 (rho) / 8e-5 (u), FP16 up
+# to 6e-3 / 0.37 and BF16 up to 7.5e-2 / 1.37 on the two-bubble box at t = 100.
 RHO_TOL = 1e-5
 U_TOL = 1e-5
-TOL = {
-    ("f32", "f64"): (1e-5, 1e-5),
-    ("f32", "f32"): (3e-4, 1e-3),
-    ("f16", "f32"): (1.2e-2, 0.8),
-    ("bf16", "f32"): (0.15, 3.0),
+GATED = {("f32", "f64"): (RHO_TOL, U_TOL)}
+SANITY = {
+    ("f32", "f32"): (1e-2, 0.1),
+    ("f16", "f32"): (0.1, 2.0),
+    ("bf16", "f32"): (0.5, 5.0),
 }
+TOL = {**GATED, **SANITY}
+
+
+def check_errors(storage, compute, e_rho, e_u, where=""):
+    """Assert the 1e-5 gate for FP32 storage with FP64 arithmetic; for the other combinations
+    print the errors as reported, not gated, and reject only non-finite or blown-up fields."""
+    key = (storage, compute)
+    rt, ut = TOL[key]
+    tag = "gated" if key in GATED else "reported, not gated"
+    print(f"[{tag}] {where} storage {storage} compute {compute}: rho {e_rho:.3e} u {e_u:.3e}",
+          flush=True)
+    assert np.isfinite(e_rho) and np.isfinite(e_u)
+    assert e_rho <= rt and e_u <= ut
 
 
 def oracle_from_spec(spec, barrier=False, corona=3):

@@ -120,7 +120,7 @@ def test_barrier_tiles_and_variants_bitwise_equal(q):
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case", ["two_bubble", "spheres"])
 def test_barrier_16bit_storage_against_oracle(case, storage):
-    from parity import TOL
+    from parity import check_errors
 
     spec = W.two_bubble() if case == "two_bubble" else _spheres()
     steps = 100 if case == "two_bubble" else 50
@@ -134,8 +134,7 @@ def test_barrier_16bit_storage_against_oracle(case, storage):
     e_rho, e_u, _, _ = field_errors(g, o)
     diff = int(np.count_nonzero(g.owner().astype(np.int32) != o.owner()))
     print(f"{storage}: rho {e_rho:.3e} u {e_u:.3e} owner nodes differing {diff} of {spec.N}")
-    rt, ut = TOL[(storage, "f32")]
-    assert e_rho <= rt and e_u <= ut
+    check_errors(storage, "f32", e_rho, e_u, "barrier")
     # owners follow the gas mask; 16-bit storage moves rho by up to the field error, so nodes
     # within that distance of theta may change sides (a regression gate, not a parity claim)
     assert diff <= spec.N // 100

@@ -96,7 +96,11 @@ def test_no_nuclei_is_liquid_only(storage, compute):
     spec = _spec(19, (48, 40, 36), np.zeros((0, 3)), [], K=25)
     _announce(f"no nuclei 48x40x36 storage={storage} compute={compute}")
     g, o, e_rho, e_u, tg, to = _compare(spec, 100, storage=storage, compute=compute)
+    # FP32 storage with FP64 arithmetic is gated at 1e-5; the other combinations are reported,
+    # not gated (their bounds only reject blown-up fields)
     rt, ut = TOL[(storage, compute)]
+    tag = "gated" if (storage, compute) == ("f32", "f64") else "reported, not gated"
+    print(f"[{tag}] no nuclei storage {storage} compute {compute}: rho {e_rho:.3e} u {e_u}")
     assert e_rho <= rt and _u_ok(e_u, ut, U_FLOOR if compute == "f64" else U_FLOOR32)
     assert not np.any(g.last_labels()) and not np.any(o.labels())
     assert g.bubbles() == [] and g.merge_events() == [] and o.events() == []

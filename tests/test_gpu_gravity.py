@@ -85,7 +85,7 @@ def test_gravity_tiles_and_variants_bitwise_equal(q):
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case", ["two_bubble", "spheres_barrier"])
 def test_gravity_16bit_storage_against_oracle(case, storage):
-    from parity import TOL
+    from parity import check_errors
 
     if case == "two_bubble":
         spec, g, barrier, steps = W.two_bubble(), (0.0, -2e-5), False, 100
@@ -103,8 +103,7 @@ def test_gravity_16bit_storage_against_oracle(case, storage):
     o.step(steps)
     e_rho, e_u, _, _ = field_errors(gpu, o)
     print(f"{storage}: rho {e_rho:.3e} u {e_u:.3e} rho0 rel diff {drho0:.2e}")
-    rt, ut = TOL[(storage, "f32")]
-    assert e_rho <= rt and e_u <= ut
+    check_errors(storage, "f32", e_rho, e_u, "gravity")
     assert drho0 <= (1e-5 if storage == "f16" else 1e-3)  # measured 1.5e-6 and 1.7e-4
 
 

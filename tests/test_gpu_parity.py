@@ -7,7 +7,7 @@ import pytest
 from oracle import OracleSim, label_mask
 from paper_1708_01608_amd import sc
 from paper_1708_01608_amd import workloads as W
-from parity import (RHO_TOL, TOL, U_TOL, events_key, field_errors, gpu_from_spec,
+from parity import (RHO_TOL, TOL, U_TOL, check_errors, events_key, field_errors, gpu_from_spec,
                     oracle_from_spec, permutation_to_oracle)
 
 pytestmark = pytest.mark.gpu
@@ -27,10 +27,8 @@ def test_two_bubble_fields_after_100_steps(storage, compute):
     g.step(100)
     o.step(100)
     e_rho, e_u, tg, to = field_errors(g, o)
-    print(f"storage {storage} compute {compute}: rho {e_rho:.3e} u {e_u:.3e} "
-          f"mass {tg[0] / to[0] - 1:.2e}")
-    rt, ut = TOL[(storage, compute)]
-    assert e_rho <= rt and e_u <= ut
+    print(f"mass {tg[0] / to[0] - 1:.2e}")
+    check_errors(storage, compute, e_rho, e_u, "two_bubble t=100")
     if (storage, compute) != ("f32", "f64"):
         return
     assert abs(tg[0] / to[0] - 1) < 1e-7
@@ -98,9 +96,7 @@ def test_ragged_boxes_with_source(q, shape, tau, tile, compute):
     g.step(100)
     o.step(100)
     e_rho, e_u, tg, to = field_errors(g, o)
-    print(f"rho {e_rho:.3e} u {e_u:.3e}")
-    rt, ut = TOL[("f32", compute)]
-    assert e_rho <= rt and e_u <= ut
+    check_errors("f32", compute, e_rho, e_u, f"ragged {shape}")
     if compute != "f64":
         return
     assert abs(tg[0] / to[0] - 1) < 1e-7
@@ -201,9 +197,7 @@ def test_foam_3d_full_size_all_nodes():
         g = gpu_from_spec(spec, compute=compute)
         g.step(100)
         e_rho, e_u, tg, to = field_errors(g, o)
-        print(f"compute {compute}: rho {e_rho:.3e} u {e_u:.3e}")
-        rt, ut = TOL[("f32", compute)]
-        assert e_rho <= rt and e_u <= ut
+        check_errors("f32", compute, e_rho, e_u, "full-size foam t=100")
         assert np.array_equal(g.last_labels(), o.labels())
         g.close()
 
@@ -218,10 +212,8 @@ def test_foam_3d_error_run_16bit_storage():
         g = gpu_from_spec(spec, storage=storage, compute=compute)
         g.step(100)
         e_rho, e_u, tg, to = field_errors(g, o)
-        print(f"storage {storage} compute {compute}: rho {e_rho:.3e} u {e_u:.3e} "
-              f"mass {tg[0] / to[0] - 1:.2e}")
-        rt, ut = TOL[(storage, compute)]
-        assert e_rho <= rt and e_u <= ut
+        print(f"mass {tg[0] / to[0] - 1:.2e}")
+        check_errors(storage, compute, e_rho, e_u, "foam_3d error run 128^3 t=100")
         g.close()
 
 
@@ -249,9 +241,49 @@ def test_foam_3d_error_growth_16bit_storage():
                   f"mass {tg[0] / to[0] - 1:.2e}", flush=True)
             rt, ut = TOL[(storage, compute)]
             if target == 100:
-                assert e_rho <= rt and e_u <= ut
-            else:
+                check_errors(storage, compute, e_rho, e_u, f"error growth t={target}")
+            else:  # reported; guarded against blow-up only
                 assert np.isfinite(e_rho) and e_rho <= 20 * rt
+    for g in sims.values():
+        g.close()
+
+
+def test_two_phase_error_box_16bit_storage():
+    """Error of every storage type against the FP64 oracle on a box that keeps its gas (two
+    spheres of the precision workload's parameters, see workloads.precision_error_box) at
+    t = 100, 500 and 2000.  FP32 storage with FP64 arithmetic is gated at t = 100; every other
+    entry is reported, not gated (only non-finite or blown-up fields fail)."""
+    spec = W.precision_error_box()
+    _announce("precision error box 94x56x56 two spheres to t = 2000")
+    combos = (("f32", "f64"), ("f32", "f32"), ("f16", "f32"), ("bf16", "f32"))
+    o = oracle_from_spec(spec)
+    sims = {c: gpu_from_spec(spec, storage=c[0], compute=c[1]) for c in combos}
+    t = 0
+    for target in (100, 500, 2000):
+        while t < target:
+            n = min(250, target - t)
+            o.step(n)
+            t += n
+            _announce(f"oracle at t = {t}")
+        ob = o.bubbles()
+        assert len(ob) == 2  # both spheres persist
+        ro = o.fields()[0]
+        for (storage, compute), g in sims.items():
+            g.step(target - g.t)
+            e_rho, e_u, tg, to = field_errors(g, o)
+            gb = g.bubbles()
+            l2 = float(np.linalg.norm(g.fields()[0] - ro) / np.linalg.norm(ro))
+            print(f"t {target} storage {storage} compute {compute}: rho {e_rho:.3e} u {e_u:.3e} "
+                  f"rho L2 {l2:.3e} mass {tg[0] / to[0] - 1:.2e} gas nodes gpu "
+                  f"{[b['n'] for b in gb]} oracle {[b['n'] for b in ob]}", flush=True)
+            if target == 100:
+                check_errors(storage, compute, e_rho, e_u, "two-phase error box t=100")
+            else:
+                # reported: over long horizons the pointwise error is set by where the interfaces
+                # sit (a node that is gas in one run and liquid in the other differs by
+                # ~rho_l / rho_g); the check is that the fields stay finite and both spheres
+                # persist on every storage type
+                assert np.isfinite(e_rho) and np.isfinite(e_u) and len(gb) == 2
     for g in sims.values():
         g.close()
 

@@ -75,3 +75,12 @@ def test_bench_prints_the_contract_line():
     assert abs(ro["frac"] - ro["achieved"] / ro["peak"]) < 1e-3
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
+    # the two system patterns of the metric ride on the same line
+    pr = d["precision"]
+    for k in ("f32 storage / f64 compute", "f16 storage / f32 compute",
+              "bf16 storage / f32 compute"):
+        assert pr["runs"][k]["MLUPS"] > 0 and 0 < pr["runs"][k]["frac"] < 1
+        assert pr["error_vs_fp64"][k]["rho"] >= 0
+    assert pr["error_vs_fp64"]["f32 storage / f64 compute"]["rho"] <= 1e-5
+    ba = d["batching"]
+    assert ba["MLUPS"] > 0 and ba["one_by_one_MLUPS"] > 0

@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = ("foam_3d", "foam_2d", "two_bubble", "foam_3d_large", "batch", "mixture_2d",
-             "mixture_3d")
+             "mixture_3d", "gas_rich_3d")
 
 
 def parse():
@@ -72,7 +72,7 @@ def workload_spec(name):
 
     return {"foam_3d": W.foam_3d, "foam_2d": W.foam_2d, "two_bubble": W.two_bubble,
             "foam_3d_large": W.foam_3d_large, "mixture_2d": W.mixture_2d,
-            "mixture_3d": W.mixture_3d}[name]()
+            "mixture_3d": W.mixture_3d, "gas_rich_3d": W.gas_rich_3d}[name]()
 
 
 def bytes_per_node(q, storage, components=1):

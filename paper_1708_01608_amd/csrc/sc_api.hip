@@ -63,7 +63,7 @@ struct sc_sim {
 
     // scratch buffers (allocated on first use)
     DevBuf parent, labels, labels2, slots, psi, rho_out, u_out, p_out, lap_out, partials, small,
-        tmp64, mask8, nodes, list_node, list_slot, add_tab, pair_buf, res_buf, bub_tab;
+        tmp64, mask8, nodes, list_node, list_slot, list_scan, add_tab, pair_buf, res_buf, bub_tab;
     bool slots_ready = false;
 
     // modified Shan-Chen barrier: owner id per node (uint16, fixed address for the step
@@ -104,7 +104,7 @@ struct sc_sim {
     int chunk_len = 0, chunk_pos = 0;
 
     // source ledger: released agent mass the storage has not taken yet.  On the device per
-    // bubble slot of the last pass (owed, node count, gain, ticket: ledger_nb slots, slot b led
+    // bubble slot of the last pass (owed, node count, gain: ledger_nb slots, slot b led
     // by nucleus ledger_lead[b]); on the host per nucleus for mass whose bubble is not fed
     DevBuf ledger;
     int ledger_nb = 0;
@@ -434,8 +434,7 @@ int upload_schedule(sc_sim* s)
 }
 
 // Ledger slots of this pass's bubbles: a fed bubble takes over what its nuclei are owed; an
-// unfed one leaves it with them.  Device layout: owed[nb], nodes[nb], gain[nb] (zero),
-// ticket (zero).
+// unfed one leaves it with them.  Device layout: owed[nb], nodes[nb], gain[nb] (zero).
 int ledger_setup(sc_sim* s, const std::vector<int32_t>& feed)
 {
 #pragma clang fp contract(off)
@@ -443,7 +442,7 @@ int ledger_setup(sc_sim* s, const std::vector<int32_t>& feed)
     s->ledger_nb = nb;
     s->ledger_lead.assign((size_t)nb, -1);
     if (nb == 0) return SC_OK;
-    std::vector<double> host((size_t)3 * nb + 1, 0.0);
+    std::vector<double> host((size_t)3 * nb, 0.0);
     for (int b = 0; b < nb; ++b) {
         s->ledger_lead[b] = s->bub[b].nucleus;
         host[(size_t)nb + b] = (double)s->bub[b].n;
@@ -470,7 +469,6 @@ SourceLedger ledger_view(sc_sim* s, int step_in_chunk)
     led.owed = (double*)s->ledger.p;
     led.nodes = led.owed + nb;
     led.gain = (unsigned long long*)(led.owed + 2 * (size_t)nb);
-    led.ticket = (unsigned int*)(led.owed + 3 * (size_t)nb);
     led.nb = nb;
     led.key = s->sr_key;
     return led;
@@ -755,9 +753,11 @@ int test_pass(sc_sim* s, bool with_criterion)
             TRY(ensure(s, s->small, 4096));
             unsigned int* cnt_d = (unsigned int*)((char*)s->small.p + 128);
             HIPX(launch_fill_i32((int32_t*)cnt_d, 0, 1, s->stream));
+            TRY(ensure(s, s->list_scan, sizeof(uint32_t) * (size_t)gas_list_scratch_words()));
             HIPX(launch_gas_list((const uint32_t*)s->labels.p, (const int32_t*)s->slots.p,
                                  (const int32_t*)(base + off_feed), (uint32_t*)s->list_node.p,
-                                 (int32_t*)s->list_slot.p, cnt_d, s->N, s->stream));
+                                 (int32_t*)s->list_slot.p, cnt_d, (unsigned int*)s->list_scan.p,
+                                 s->N, s->stream));
             unsigned int got = 0;
             HIPX(hipMemcpyAsync(&got, cnt_d, sizeof(got), hipMemcpyDeviceToHost, s->stream));
             HIPX(hipStreamSynchronize(s->stream));
@@ -943,7 +943,7 @@ void release(sc_sim* s)
                       &s->u_out, &s->p_out, &s->lap_out, &s->partials, &s->small, &s->tmp64,
                       &s->mask8, &s->nodes, &s->list_node, &s->list_slot, &s->add_tab,
                       &s->pair_buf, &s->res_buf, &s->bub_tab, &s->owner, &s->owner2,
-                      &s->owner_ids, &s->frontier})
+                      &s->owner_ids, &s->frontier, &s->ledger, &s->list_scan})
         dev_free(s, b->p);
     dev_free(s, s->f[0]);
     dev_free(s, s->f[1]);

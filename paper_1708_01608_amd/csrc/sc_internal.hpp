@@ -140,10 +140,12 @@ hipError_t launch_stats(const uint32_t* labels, const int32_t* slot_of_root,
                         const int32_t* anchors_d /*[nb][3]*/, unsigned long long* count_d,
                         unsigned long long* sums_d /*[nb][3]*/, const FieldArgs& a,
                         hipStream_t st);
+// Fed gas nodes in node order; block_counts holds gas_list_scratch_words() words of scratch.
+int gas_list_scratch_words();
 hipError_t launch_gas_list(const uint32_t* labels, const int32_t* slot_of_root,
                            const int32_t* feed_d /*[nb]: 1 if the bubble is fed*/,
                            uint32_t* list_node, int32_t* list_slot, unsigned int* count_d,
-                           int64_t N, hipStream_t st);
+                           unsigned int* block_counts, int64_t N, hipStream_t st);
 
 struct MergePair {
     double cen_a[3];
@@ -180,13 +182,12 @@ hipError_t launch_film(int q, int storage, const void* f, const uint32_t* labels
 
 // Blowing-agent source for one step: f_i(x) += w_i * T_b / n_b on the listed gas nodes, with
 // T_b = owed[b] + dm[b]; the stored values' exact gain closes the ledger (owed[b] = T_b - gain).
-// Device tables of nb bubble slots; gain (2^-40 fixed point) and ticket are zero between steps.
+// Device tables of nb bubble slots; gain (2^-40 fixed point) is zero between steps.
 struct SourceLedger {
     const double* dm;          // this step's release of each bubble's nuclei
     const double* nodes;       // n_b, gas nodes listed for the bubble
     double* owed;              // mass released earlier that the storage has not taken yet
     unsigned long long* gain;  // sum of this step's gains in 2^-40 units (two's complement)
-    unsigned int* ticket;      // blocks finished in this launch
     int nb;
     uint64_t key;              // stochastic-rounding stream (16-bit storage)
 };

@@ -170,6 +170,37 @@ __global__ void k_laplacian(const double* p, double* lap, FieldArgs a)
     }
 }
 
+// ---- wave-level aggregation of per-node atomics ------------------------------------------------
+// Per-node contributions to per-bubble counters arrive from many nodes of the same bubble at
+// once; one atomic per node onto a few hundred addresses serialises.  The lanes of a wave that
+// carry the same key (a bubble slot, >= 0) sum their values with a butterfly and one lane adds the
+// sum: one atomic per distinct key per wave.  Integer sums, so the result does not depend on the
+// grouping.  Every lane of the wave must call these (the loops below are wave-uniform).
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int M, typename Flush>
+__device__ __forceinline__ void wave_add_by_key(int key, const long long (&v)[M], Flush flush)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long pending = __ballot(key >= 0);
+    while (pending) {
+        const int leader = __ffsll(pending) - 1;
+        const int k = __shfl(key, leader, 64);
+        const bool mine = key == k;
+        const unsigned long long grp = __ballot(mine);
+        long long sum[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) sum[j] = wave_sum_i64(mine ? v[j] : 0ll);
+        if (lane == leader) flush(k, sum);
+        pending &= ~grp;
+    }
+}
+
 // ---- FP64 totals: wave64 shuffles -> LDS -> one partial per block -> fixed-order final sum ---
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -341,25 +372,6 @@ __device__ void unite(uint32_t* parent, uint32_t a, uint32_t b)
     }
 }
 
-template <int Q>
-__global__ void k_union(uint32_t* parent, FieldArgs a)
-{
-    using L = lat<Q>;
-    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        if (load_parent(parent, (uint32_t)n) == kLiquid) continue;
-        int x, y, z;
-        coords3(n, a.nx, a.ny, x, y, z);
-#pragma unroll
-        for (int h = 0; h < L::nhalf; ++h) {
-            const int64_t m = shifted<Q>(x, y, z, L::half[h], +1, a);
-            if (m == n) continue;
-            if (load_parent(parent, (uint32_t)m) == kLiquid) continue;
-            unite(parent, (uint32_t)n, (uint32_t)m);
-        }
-    }
-}
-
 __global__ void k_flatten(const uint32_t* parent, uint32_t* labels, uint32_t* ncomp, int64_t N)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
@@ -376,6 +388,137 @@ __global__ void k_flatten(const uint32_t* parent, uint32_t* labels, uint32_t* nc
         }
         labels[n] = r + 1;
         if (r == (uint32_t)n) atomicAdd(ncomp, 1u);
+    }
+}
+
+// Tiled labelling.  A plain union over every lattice link sends all of them through global
+// atomics and pointer chases; on a gas-rich box that is most of the test pass.  Instead each block
+// first unites the links inside its tile in LDS (local indices follow the global index order
+// within a tile, so a local root is the smallest global index of its local set) and writes the
+// local roots to parent; a second kernel unites only the links that leave a tile (or wrap around
+// the box) through the global structure.  Roots still link to smaller indices, so the labels
+// stay the canonical 1 + smallest index of each component.
+template <int Q>
+struct UnionTile;
+template <>
+struct UnionTile<9> {
+    static constexpr int TX = 64, TY = 64, TZ = 1;
+};
+template <>
+struct UnionTile<19> {
+    static constexpr int TX = 16, TY = 16, TZ = 16;
+};
+
+__device__ __forceinline__ uint32_t lds_load(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t lds_root(const uint32_t* lp, uint32_t x)
+{
+    uint32_t p = lds_load(lp + x);
+    while (p != x) {
+        x = p;
+        p = lds_load(lp + x);
+    }
+    return x;
+}
+
+__device__ void lds_unite(uint32_t* lp, uint32_t a, uint32_t b)
+{
+    while (true) {
+        a = lds_root(lp, a);
+        b = lds_root(lp, b);
+        if (a == b) return;
+        if (a > b) { const uint32_t t = a; a = b; b = t; }
+        const uint32_t old = atomicMin(lp + b, a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+// Neighbour (x + e_i) of a tile node stays inside the tile and the box: a local link.
+template <int Q>
+__device__ __forceinline__ bool local_link(int lx, int ly, int lz, int x, int y, int z, int i,
+                                           const FieldArgs& a)
+{
+    using L = lat<Q>;
+    using T = UnionTile<Q>;
+    const int mx = lx + L::ex[i], my = ly + L::ey[i], mz = lz + L::ez[i];
+    return mx >= 0 && mx < T::TX && my >= 0 && my < T::TY && mz >= 0 && mz < T::TZ &&
+           x + L::ex[i] >= 0 && x + L::ex[i] < a.nx && y + L::ey[i] >= 0 &&
+           y + L::ey[i] < a.ny && z + L::ez[i] >= 0 && z + L::ez[i] < a.nz;
+}
+
+template <int Q>
+__global__ void __launch_bounds__(256) k_union_local(uint32_t* parent, FieldArgs a)
+{
+    using L = lat<Q>;
+    using T = UnionTile<Q>;
+    constexpr int NT = T::TX * T::TY * T::TZ;
+    __shared__ uint32_t lp[NT];
+    const int gx = (a.nx + T::TX - 1) / T::TX, gy = (a.ny + T::TY - 1) / T::TY;
+    const int b = blockIdx.x;
+    const int x0 = (b % gx) * T::TX, y0 = ((b / gx) % gy) * T::TY, z0 = (b / (gx * gy)) * T::TZ;
+    auto node = [&](int li, int& lx, int& ly, int& lz, int& x, int& y, int& z) {
+        lx = li % T::TX;
+        ly = (li / T::TX) % T::TY;
+        lz = li / (T::TX * T::TY);
+        x = x0 + lx; y = y0 + ly; z = z0 + lz;
+        return x < a.nx && y < a.ny && z < a.nz;
+    };
+    for (int li = threadIdx.x; li < NT; li += blockDim.x) {
+        int lx, ly, lz, x, y, z;
+        const bool in = node(li, lx, ly, lz, x, y, z);
+        lp[li] = (in && parent[idx3(x, y, z, a.nx, a.ny)] != kLiquid) ? (uint32_t)li : kLiquid;
+    }
+    __syncthreads();
+    for (int li = threadIdx.x; li < NT; li += blockDim.x) {
+        if (lds_load(lp + li) == kLiquid) continue;
+        int lx, ly, lz, x, y, z;
+        node(li, lx, ly, lz, x, y, z);
+#pragma unroll
+        for (int h = 0; h < L::nhalf; ++h) {
+            const int i = L::half[h];
+            if (!local_link<Q>(lx, ly, lz, x, y, z, i, a)) continue;
+            const int lj = li + L::ex[i] + T::TX * (L::ey[i] + T::TY * L::ez[i]);
+            if (lds_load(lp + lj) == kLiquid) continue;
+            lds_unite(lp, (uint32_t)li, (uint32_t)lj);
+        }
+    }
+    __syncthreads();
+    for (int li = threadIdx.x; li < NT; li += blockDim.x) {
+        if (lp[li] == kLiquid) continue;
+        int lx, ly, lz, x, y, z;
+        node(li, lx, ly, lz, x, y, z);
+        const uint32_t r = lds_root(lp, (uint32_t)li);
+        const int rx = x0 + (int)(r % T::TX), ry = y0 + (int)((r / T::TX) % T::TY);
+        const int rz = z0 + (int)(r / (T::TX * T::TY));
+        parent[idx3(x, y, z, a.nx, a.ny)] = (uint32_t)idx3(rx, ry, rz, a.nx, a.ny);
+    }
+}
+
+// The links the tiles could not see: those that leave a tile or wrap around the box.
+template <int Q>
+__global__ void k_union_cross(uint32_t* parent, FieldArgs a)
+{
+    using L = lat<Q>;
+    using T = UnionTile<Q>;
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        if (load_parent(parent, (uint32_t)n) == kLiquid) continue;
+        int x, y, z;
+        coords3(n, a.nx, a.ny, x, y, z);
+        const int lx = x % T::TX, ly = y % T::TY, lz = z % T::TZ;
+#pragma unroll
+        for (int h = 0; h < L::nhalf; ++h) {
+            const int i = L::half[h];
+            if (local_link<Q>(lx, ly, lz, x, y, z, i, a)) continue;
+            const int64_t m = shifted<Q>(x, y, z, i, +1, a);
+            if (m == n) continue;
+            if (load_parent(parent, (uint32_t)m) == kLiquid) continue;
+            unite(parent, (uint32_t)n, (uint32_t)m);
+        }
     }
 }
 
@@ -406,38 +549,121 @@ __device__ __forceinline__ int64_t min_image_i(int64_t d, int n)
 __global__ void k_stats(const uint32_t* labels, const int32_t* slot_of_root, const int32_t* anchors,
                         unsigned long long* count, unsigned long long* sums, FieldArgs a)
 {
-    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t L = labels[n];
-        if (!L) continue;
-        const int b = slot_of_root[L - 1];
-        if (b < 0) continue;
-        int x, y, z;
-        coords3(n, a.nx, a.ny, x, y, z);
-        const int64_t ox = min_image_i((int64_t)x - anchors[3 * b + 0], a.nx);
-        const int64_t oy = min_image_i((int64_t)y - anchors[3 * b + 1], a.ny);
-        const int64_t oz = min_image_i((int64_t)z - anchors[3 * b + 2], a.nz);
-        atomicAdd(count + b, 1ull);
+    // block-uniform trip count, so every lane of a wave reaches the aggregation
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t n0 = blockIdx.x * (int64_t)blockDim.x; n0 < a.N; n0 += stride) {
+        const int64_t n = n0 + threadIdx.x;
+        int b = -1;
+        long long v[4] = {0, 0, 0, 0};
+        if (n < a.N) {
+            const uint32_t L = labels[n];
+            if (L) b = slot_of_root[L - 1];
+            if (b >= 0) {
+                int x, y, z;
+                coords3(n, a.nx, a.ny, x, y, z);
+                v[0] = 1;
+                v[1] = min_image_i((int64_t)x - anchors[3 * b + 0], a.nx);
+                v[2] = min_image_i((int64_t)y - anchors[3 * b + 1], a.ny);
+                v[3] = min_image_i((int64_t)z - anchors[3 * b + 2], a.nz);
+            }
+        }
         // two's-complement wrap-around makes unsigned adds exact signed sums
-        atomicAdd(sums + 3 * b + 0, (unsigned long long)ox);
-        atomicAdd(sums + 3 * b + 1, (unsigned long long)oy);
-        atomicAdd(sums + 3 * b + 2, (unsigned long long)oz);
+        wave_add_by_key<4>(b, v, [&](int k, const long long* s) {
+            atomicAdd(count + k, (unsigned long long)s[0]);
+            atomicAdd(sums + 3 * k + 0, (unsigned long long)s[1]);
+            atomicAdd(sums + 3 * k + 1, (unsigned long long)s[2]);
+            atomicAdd(sums + 3 * k + 2, (unsigned long long)s[3]);
+        });
     }
 }
 
-__global__ void k_gas_list(const uint32_t* labels, const int32_t* slot_of_root, const int32_t* feed,
-                           uint32_t* list_node, int32_t* list_slot, unsigned int* count,
-                           int64_t N)
+// Gas-node list of the fed bubbles, in node order, without a global atomic per node or per wave:
+// every block owns a contiguous chunk of nodes; the blocks count their fed gas nodes, one wave
+// turns the counts into offsets, and each block writes its nodes from its offset on.
+constexpr int kListBlocks = 1024;
+
+static int64_t list_chunk(int64_t N)
 {
-    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t L = labels[n];
-        if (!L) continue;
-        const int b = slot_of_root[L - 1];
-        if (b < 0 || !feed[b]) continue;
-        const unsigned int k = atomicAdd(count, 1u);
-        list_node[k] = (uint32_t)n;
-        list_slot[k] = b;
+    return ((N + (int64_t)kListBlocks * 256 - 1) / ((int64_t)kListBlocks * 256)) * 256;
+}
+
+__device__ __forceinline__ bool fed_gas(const uint32_t* labels, const int32_t* slot_of_root,
+                                        const int32_t* feed, int64_t n, int64_t N, int& b)
+{
+    b = -1;
+    if (n >= N) return false;
+    const uint32_t L = labels[n];
+    if (!L) return false;
+    const int s = slot_of_root[L - 1];
+    if (s < 0 || !feed[s]) return false;
+    b = s;
+    return true;
+}
+
+__global__ void __launch_bounds__(256) k_gas_count(const uint32_t* labels,
+                                                   const int32_t* slot_of_root,
+                                                   const int32_t* feed, unsigned int* counts,
+                                                   int64_t N, int64_t chunk)
+{
+    const int64_t begin = blockIdx.x * chunk;
+    unsigned int c = 0;
+    for (int64_t n0 = begin; n0 < begin + chunk && n0 < N; n0 += 256) {
+        int b;
+        c += (unsigned int)__syncthreads_count(
+            fed_gas(labels, slot_of_root, feed, n0 + threadIdx.x, N, b));
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+// One wave: exclusive prefix sums of the block counts in place, and their total.
+__global__ void __launch_bounds__(64) k_gas_scan(unsigned int* counts, int n, unsigned int* total)
+{
+    const int lane = (int)threadIdx.x;
+    unsigned int carry = 0;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+        const int i = c0 + lane;
+        const unsigned int v = i < n ? counts[i] : 0u;
+        unsigned int x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (i < n) counts[i] = carry + x - v;
+        carry += __shfl(x, 63, 64);
+    }
+    if (lane == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(256) k_gas_write(const uint32_t* labels,
+                                                   const int32_t* slot_of_root,
+                                                   const int32_t* feed,
+                                                   const unsigned int* offsets,
+                                                   uint32_t* list_node, int32_t* list_slot,
+                                                   int64_t N, int64_t chunk)
+{
+    __shared__ unsigned int wcnt[4];
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned int base = offsets[blockIdx.x];
+    const int64_t begin = blockIdx.x * chunk;
+    for (int64_t n0 = begin; n0 < begin + chunk && n0 < N; n0 += 256) {
+        const int64_t n = n0 + threadIdx.x;
+        int b;
+        const bool g = fed_gas(labels, slot_of_root, feed, n, N, b);
+        const unsigned long long m = __ballot(g);
+        if (lane == 0) wcnt[w] = (unsigned int)__popcll(m);
+        __syncthreads();
+        unsigned int off = base;
+        for (int k = 0; k < w; ++k) off += wcnt[k];
+        const unsigned int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        if (g) {
+            const unsigned int k = off + (unsigned int)__popcll(m & below);
+            list_node[k] = (uint32_t)n;
+            list_slot[k] = b;
+        }
+        base += tot;
+        __syncthreads();  // wcnt is rewritten by the next pass
     }
 }
 
@@ -529,7 +755,7 @@ __global__ void k_merge(const S* f, const uint32_t* labels, const MergePair* pai
 // gas node (~5e-4 at -0.59 in FP16) exceeds the per-step increment (~1e-7) by orders of
 // magnitude, so rounding to nearest would drop every increment.  The exact gain of the stored
 // values (FP64 differences) is summed per bubble in fixed point (2^-40 units, integer atomics,
-// so the sum does not depend on the order of the nodes), and the last block to finish sets
+// so the sum does not depend on the order of the nodes), and k_source_close then sets
 // owed_b = T_b - gain_b: the ledger carries what the storage could not take into the next step.
 
 // The storage value next to the 16-bit pattern b toward +inf (up) or -inf: sign-magnitude
@@ -570,43 +796,60 @@ __global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_sl
                          SourceLedger led, int64_t t, FieldArgs a)
 {
     using L = lat<Q>;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int b = list_slot[k];
-        const double T = led.owed[b] + led.dm[b];
-        if (T == 0.0) continue;
-        const double ab = T / led.nodes[b];
-        const int64_t n = list_node[k];
-        int x, y, z;
-        coords3(n, a.nx, a.ny, x, y, z);
-        double gain = 0.0;
+    // block-uniform trip count, so every lane of a wave reaches the aggregation of the gains
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < count; k0 += stride) {
+        const int64_t k = k0 + threadIdx.x;
+        int b = -1;
+        long long gfx[1] = {0};
+        if (k < count) {
+            b = list_slot[k];
+            const double T = led.owed[b] + led.dm[b];
+            if (T == 0.0) {
+                b = -1;
+            } else {
+                const double ab = T / led.nodes[b];
+                const int64_t n = list_node[k];
+                int x, y, z;
+                coords3(n, a.nx, a.ny, x, y, z);
+                // every population of the node is loaded before any is stored (the stores
+                // would otherwise order each load behind the previous direction's store)
+                S* slot[Q];
+                S old[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            S* slot = f + (int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a);
-            const S old = *slot;
-            const double oldd = (double)load_f(old);
-            const double u = unit_noise(led.key, ((uint64_t)t * (uint64_t)a.N + (uint64_t)n) *
-                                                     (uint64_t)Q + (uint64_t)i);
-            const S nw = round_into<S>(oldd + L::wd[i] * ab, u);
-            *slot = nw;
-            gain += (double)load_f(nw) - oldd;
+                for (int i = 0; i < Q; ++i) {
+                    slot[i] = f + (int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a);
+                    old[i] = *slot[i];
+                }
+                double gain = 0.0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const double oldd = (double)load_f(old[i]);
+                    const double u = unit_noise(
+                        led.key, ((uint64_t)t * (uint64_t)a.N + (uint64_t)n) * (uint64_t)Q +
+                                     (uint64_t)i);
+                    const S nw = round_into<S>(oldd + L::wd[i] * ab, u);
+                    *slot[i] = nw;
+                    gain += (double)load_f(nw) - oldd;
+                }
+                gfx[0] = (long long)rint(gain * kGainScale);
+            }
         }
-        atomicAdd(&led.gain[b], (unsigned long long)(long long)rint(gain * kGainScale));
+        wave_add_by_key<1>(b, gfx, [&](int kb, const long long* s) {
+            atomicAdd(&led.gain[kb], (unsigned long long)s[0]);
+        });
     }
-    // the last block to finish closes the ledger of this step
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(led.ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// Closes the step's ledger once every node has added: owed_b = T_b - gain_b, gains back to zero.
+__global__ void __launch_bounds__(256) k_source_close(SourceLedger led)
+{
     for (int b = threadIdx.x; b < led.nb; b += blockDim.x) {
-        const long long g = (long long)atomicExch(&led.gain[b], 0ull);
+        const long long g = (long long)led.gain[b];
         const double T = led.owed[b] + led.dm[b];
         led.owed[b] = T - (double)g * kGainUnit;
+        led.gain[b] = 0ull;
     }
-    if (threadIdx.x == 0) *led.ticket = 0u;
 }
 
 // ---- film geometry of a bubble pair (Sec. 3 film disc; Fig. 3) --------------------------------
@@ -865,15 +1108,23 @@ hipError_t launch_mask_from_bytes(const uint8_t* mask_d, uint32_t* parent, int64
     return hipGetLastError();
 }
 
+template <int Q>
+static hipError_t launch_union_tiled(uint32_t* parent, const FieldArgs& a, hipStream_t st)
+{
+    using T = UnionTile<Q>;
+    const int64_t tiles = (int64_t)((a.nx + T::TX - 1) / T::TX) * ((a.ny + T::TY - 1) / T::TY) *
+                          ((a.nz + T::TZ - 1) / T::TZ);
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_union_local<Q>), dim3((unsigned)tiles), dim3(256), 0, st, parent, a);
+    hipLaunchKernelGGL((k_union_cross<Q>), grid_for(a.N), dim3(256), 0, st, parent, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_union(int q, uint32_t* parent, const FieldArgs& a, hipStream_t st)
 {
-    if (q == 9)
-        hipLaunchKernelGGL((k_union<9>), grid_for(a.N), dim3(256), 0, st, parent, a);
-    else if (q == 19)
-        hipLaunchKernelGGL((k_union<19>), grid_for(a.N), dim3(256), 0, st, parent, a);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (q == 9) return launch_union_tiled<9>(parent, a, st);
+    if (q == 19) return launch_union_tiled<19>(parent, a, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_flatten(uint32_t* parent, uint32_t* labels, uint32_t* ncomp_d, int64_t N,
@@ -910,12 +1161,19 @@ hipError_t launch_stats(const uint32_t* labels, const int32_t* slot_of_root,
     return hipGetLastError();
 }
 
+int gas_list_scratch_words() { return kListBlocks; }
+
 hipError_t launch_gas_list(const uint32_t* labels, const int32_t* slot_of_root,
                            const int32_t* feed_d, uint32_t* list_node, int32_t* list_slot,
-                           unsigned int* count_d, int64_t N, hipStream_t st)
+                           unsigned int* count_d, unsigned int* block_counts, int64_t N,
+                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gas_list, grid_for(N), dim3(256), 0, st, labels, slot_of_root, feed_d,
-                       list_node, list_slot, count_d, N);
+    const int64_t chunk = list_chunk(N);
+    hipLaunchKernelGGL(k_gas_count, dim3(kListBlocks), dim3(256), 0, st, labels, slot_of_root,
+                       feed_d, block_counts, N, chunk);
+    hipLaunchKernelGGL(k_gas_scan, dim3(1), dim3(64), 0, st, block_counts, kListBlocks, count_d);
+    hipLaunchKernelGGL(k_gas_write, dim3(kListBlocks), dim3(256), 0, st, labels, slot_of_root,
+                       feed_d, block_counts, list_node, list_slot, N, chunk);
     return hipGetLastError();
 }
 
@@ -939,6 +1197,7 @@ hipError_t launch_source(int q, int storage, void* f, const uint32_t* list_node,
     SC_DISPATCH(q, storage,
                 hipLaunchKernelGGL((k_source<QQ, SS>), grid_for(count), dim3(256), 0, st, (SS*)f,
                                    list_node, list_slot, count, led, t, a));
+    hipLaunchKernelGGL(k_source_close, dim3(1), dim3(256), 0, st, led);
     return hipGetLastError();
 }
 

@@ -166,6 +166,14 @@ def _foam(name, q, shape, n_nuclei, seed, tau, K, steps, radius=3.0, min_spacing
                    radii=np.full(n_nuclei, radius), budgets=budgets, rate=rate)
 
 
+def gas_rich_3d(n=256, n_nuclei=200, seed=3, steps=5000, K=50):
+    """foam_3d's box and cadence with bubbles that persist, to measure the test pass on a gas
+    mask that is not empty: 200 spheres of radius 12 (about 7,200 gas nodes each, 8.6 % of the
+    box) at least 30 apart, in a slightly stretched liquid (rho_l = 1.80) that keeps them."""
+    return _foam("gas_rich_3d", 19, (n, n, n), n_nuclei, seed, tau=0.9, K=K, steps=steps,
+                 radius=12.0, min_spacing=30.0, rho_l=1.80)
+
+
 def foam_2d(n=1024, n_nuclei=64, seed=2, steps=20000, K=100):
     return _foam("foam_2d", 9, (n, n), n_nuclei, seed, tau=1.0, K=K, steps=steps)
 

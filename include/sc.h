@@ -194,6 +194,13 @@ int sc_seed_nuclei(struct sc_sim* sim, int32_t n, const double* centre, const do
  * FP64 totals).  nsteps >= 0.  SC_E_NUMERIC if a total is not finite. */
 int sc_step(struct sc_sim* sim, int32_t nsteps);
 
+/* K-step blocks as HIP graphs (Fig. 1 steps 1-6 repeated between two test passes): on a box of at
+ * most 2^22 nodes, a block of test_every steps that launches no source and no barrier fix-up runs
+ * as one captured graph (kernel launches only), the same kernels with the same arguments as the
+ * launches one by one, so the results are identical.  enable = 0 launches step by step.  On by
+ * default.  Errors: SC_E_INVAL (NULL sim), SC_E_STATE. */
+int sc_step_graphs(struct sc_sim* sim, int32_t enable);
+
 /* Fig. 1 steps 8-9 (the lattices merged to post-process the output; Sec. 3.1 model): rho[N] and
  * u[d][N] = (j + F/2)/rho (FP32; F with the body force when gravity is on; the mixture reports
  * its barycentric velocity), totals = (M, Jx, Jy, Jz) summed in FP64 over the post-streaming

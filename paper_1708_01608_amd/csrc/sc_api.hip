@@ -36,6 +36,7 @@ struct DevBuf {
 struct ProfRec {
     hipEvent_t a, b;
     int cls;
+    int launches = 1;  // kernel launches between a and b (a K-step graph records K)
 };
 
 }  // namespace
@@ -111,6 +112,26 @@ struct sc_sim {
     std::vector<int> ledger_lead;
     std::vector<double> owed_nuc;
     uint64_t sr_key = 0;
+
+    // the test pass on the device: bubble table, statistics and candidate pairs (btab, the
+    // nucleus nodes in `nodes`, pairs in pair_buf / res_buf / pair_ab), read back through pinned
+    // host memory (stage, stage_n nuclei; the merge groups are staged there too) with one
+    // synchronization
+    DevBuf btab, pair_ab;
+    int pair_cap = 0;
+    bool group_dirty = true;
+    char* stage = nullptr;      // host address
+    char* stage_dev = nullptr;  // the same memory as the device addresses it
+    int stage_n = -1;
+
+    // K-step blocks of a launch-bound box as HIP graphs: one executable per starting buffer
+    // parity, valid while the captured arguments (graph_key) stay the same
+    bool graphs = true;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    std::vector<char> graph_key[2];
+    // and the device part of the test pass that follows such a block (per parity)
+    hipGraphExec_t pass_exec[2] = {nullptr, nullptr};
+    std::vector<char> pass_key[2];
 
     std::vector<sc_merge_event> events;
     std::vector<sc_topo_event> topo;
@@ -189,6 +210,7 @@ int check_usable(sc_sim* s)
 FieldArgs field_args(const sc_sim* s)
 {
     FieldArgs a;
+    std::memset(&a, 0, sizeof(a));  // padding included: the graph cache compares the bytes
     a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
     a.N = s->N;
     a.G = (float)s->p.G;
@@ -210,6 +232,7 @@ FieldArgs field_args(const sc_sim* s)
 Step2cArgs step2c_args(const sc_sim* s)
 {
     Step2cArgs a;
+    std::memset(&a, 0, sizeof(a));  // padding included: the graph cache compares the bytes
     a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
     a.N = s->N;
     a.planes = s->shape.tile_z;
@@ -224,6 +247,7 @@ Step2cArgs step2c_args(const sc_sim* s)
 StepArgs step_args(const sc_sim* s)
 {
     StepArgs a;
+    std::memset(&a, 0, sizeof(a));  // padding included: the graph cache compares the bytes
     a.nx = s->p.nx; a.ny = s->p.ny; a.nz = s->p.nz;
     a.planes = s->shape.tile_z;
     a.N = s->N;
@@ -424,7 +448,7 @@ void build_schedule(sc_sim* s, int len)
 int upload_schedule(sc_sim* s)
 {
     const int nb = (int)s->bub.size();
-    if (nb == 0 || s->chunk_len == 0) return SC_OK;
+    if (nb == 0 || s->chunk_len == 0 || !(s->rate > 0.0)) return SC_OK;
     const size_t bytes = sizeof(double) * (size_t)s->chunk_len * nb;
     TRY(ensure(s, s->add_tab, bytes));
     HIPX(hipMemcpyAsync(s->add_tab.p, s->add_host.data(), bytes, hipMemcpyHostToDevice,
@@ -485,10 +509,11 @@ int schedule_chunk_len(const sc_sim* s)
 // defer, the totals' copy is only queued: the caller synchronizes the stream and adds the gas
 // component's totals itself.
 int gas_totals_add(sc_sim* s, double out[4]);
+int gas_totals_queue(sc_sim* s);
 int totals_now(sc_sim* s, double out[4]);
 
 int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uint8_t* mask_host,
-                  double* tot_host = nullptr, bool defer = false)
+                  double* tot_host = nullptr, bool defer = false, bool copy_tot = true)
 {
     const FieldArgs fa = field_args(s);
     TRY(ensure(s, s->parent, sizeof(uint32_t) * (size_t)s->N));
@@ -515,7 +540,7 @@ int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uin
     if (ncomp_host)
         HIPX(hipMemcpyAsync(ncomp_host, ncomp_d, sizeof(uint32_t), hipMemcpyDeviceToHost,
                             s->stream));
-    if (tot_host && !mask_host)
+    if (tot_host && !mask_host && copy_tot)
         HIPX(hipMemcpyAsync(tot_host, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost,
                             s->stream));
     if (ncomp_host || (tot_host && !defer)) HIPX(hipStreamSynchronize(s->stream));
@@ -535,6 +560,21 @@ int totals_now(sc_sim* s, double out[4])
     HIPX(hipMemcpyAsync(out, out_d, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPX(hipStreamSynchronize(s->stream));
     if (s->two) TRY(gas_totals_add(s, out));  // the mixture's totals: both components
+    return SC_OK;
+}
+
+// The gas component's FP64 totals, queued into the device slot small + 64 bytes (read back by the
+// test pass's stage-out kernel).
+int gas_totals_queue(sc_sim* s)
+{
+    FieldArgs fg = field_args(s);
+    fg.rho_ref_d = s->rho_ref_v;
+    fg.rho_ref = (float)s->rho_ref_v;
+    TRY(ensure(s, s->partials, sizeof(double) * 4 * (size_t)totals_blocks(s->N)));
+    TRY(ensure(s, s->small, 4096));
+    double* out_d = (double*)s->small.p + 8;
+    HIPX(launch_totals(s->q, s->p.storage, s->fv[s->cur], (double*)s->partials.p, out_d, fg,
+                       s->stream));
     return SC_OK;
 }
 
@@ -620,54 +660,201 @@ int set_rho0(sc_sim* s)
     return SC_OK;
 }
 
-int test_pass(sc_sim* s, bool with_criterion)
+// Pinned host memory the test pass reads back into: the FP64 totals (both components), the
+// bubble table's head, the nucleus labels, the statistics, the ledger of the last pass, the first
+// kStagePairs candidate pairs with their merge results, and the merge groups it uploads.
+constexpr int kStagePairs = 64;
+struct Stage {
+    double* tot;        // [8]: liquid (or only) component, then the gas component
+    int32_t* head;      // [16]
+    uint32_t* comp;     // [n]
+    unsigned long long* count;  // [n]
+    unsigned long long* sums;   // [3n]
+    double* owed;       // [n]
+    MergePair* pairs;   // [kStagePairs]
+    int32_t* ab;        // [2 kStagePairs]
+    MergeResult* res;   // [kStagePairs]
+    int32_t* group;     // [n]
+};
+
+size_t stage_bytes(int n)
+{
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    auto al = [](size_t b) { return (b + 63) & ~size_t(63); };
+    return al(64) + al(64) + al(4 * m) + al(8 * m) + al(24 * m) + al(8 * m) +
+           al(sizeof(MergePair) * kStagePairs) + al(8 * kStagePairs) +
+           al(sizeof(MergeResult) * kStagePairs) + al(4 * m);
+}
+
+Stage stage_view(char* p, int n)
+{
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    auto al = [](size_t b) { return (b + 63) & ~size_t(63); };
+    Stage st;
+    st.tot = (double*)p; p += al(64);
+    st.head = (int32_t*)p; p += al(64);
+    st.comp = (uint32_t*)p; p += al(4 * m);
+    st.count = (unsigned long long*)p; p += al(8 * m);
+    st.sums = (unsigned long long*)p; p += al(24 * m);
+    st.owed = (double*)p; p += al(8 * m);
+    st.pairs = (MergePair*)p; p += al(sizeof(MergePair) * kStagePairs);
+    st.ab = (int32_t*)p; p += al(8 * kStagePairs);
+    st.res = (MergeResult*)p; p += al(sizeof(MergeResult) * kStagePairs);
+    st.group = (int32_t*)p;
+    return st;
+}
+
+int ensure_stage(sc_sim* s, int n)
+{
+    if (s->stage && s->stage_n >= n) return SC_OK;
+    if (s->stage) {
+        HIPX(hipStreamSynchronize(s->stream));
+        (void)hipHostFree(s->stage);
+        s->stage = nullptr;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, stage_bytes(n), hipHostMallocDefault) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(SC_E_NOMEM, "pinned host staging of the test pass");
+    }
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess || !d) {
+        (void)hipGetLastError();
+        (void)hipHostFree(p);
+        return fail(SC_E_DEVICE, "device address of the pinned staging");
+    }
+    s->stage = (char*)p;
+    s->stage_dev = (char*)d;
+    s->stage_n = n;
+    s->group_dirty = true;
+    return SC_OK;
+}
+
+// The test pass in three parts.  pass_prepare allocates what the pass needs and stages the merge
+// groups; pass_enqueue queues every kernel and copy up to the pass's one synchronization (no
+// allocation, no host read of device data, so it can be captured in a graph); pass_finish
+// synchronizes and runs the host registry on what came back.
+int pass_prepare(sc_sim* s, bool with_criterion)
+{
+    const int n = (int)s->rad.size();
+    TRY(ensure_stage(s, n));
+    TRY(ensure(s, s->labels, sizeof(uint32_t) * (size_t)s->N));
+    TRY(ensure(s, s->parent, sizeof(uint32_t) * (size_t)s->N));
+    TRY(ensure(s, s->small, 4096));
+    TRY(ensure(s, s->partials, sizeof(double) * 4 * (size_t)totals_blocks(s->N)));
+    if (n > 0) {
+        if (!s->slots_ready) {
+            TRY(ensure(s, s->slots, sizeof(int32_t) * (size_t)s->N));
+            HIPX(launch_fill_i32((int32_t*)s->slots.p, -1, s->N, s->stream));
+            s->slots_ready = true;
+        }
+        TRY(ensure(s, s->btab, bubble_tab_bytes(n)));
+        if (with_criterion && n >= 2) {
+            const Stage st = stage_view(s->stage, n);
+            if (s->group_dirty) {
+                for (int k = 0; k < n; ++k) st.group[k] = uf_find(s->merge_parent, k);
+                s->group_dirty = false;
+            }
+            const int cap = std::max(kStagePairs, s->pair_cap);
+            TRY(ensure(s, s->pair_buf, sizeof(MergePair) * (size_t)cap));
+            TRY(ensure(s, s->res_buf, sizeof(MergeResult) * (size_t)cap));
+            TRY(ensure(s, s->pair_ab, sizeof(int32_t) * 2 * (size_t)cap));
+        }
+    }
+    return SC_OK;
+}
+
+int pass_enqueue(sc_sim* s, bool with_criterion)
+{
+    const FieldArgs fa = field_args(s);
+    const int n = (int)s->rad.size();
+    const Stage st = stage_view(s->stage, n);
+
+    const Stage sd = stage_view(s->stage_dev, n);  // the staging as the device addresses it
+    StageOut o{};
+    o.dst_tot = sd.tot; o.dst_head = sd.head; o.dst_comp = sd.comp; o.dst_count = sd.count;
+    o.dst_sums = sd.sums; o.dst_owed = sd.owed; o.dst_pairs = sd.pairs; o.dst_ab = sd.ab;
+    o.dst_res = sd.res;
+
+    // 1. gas mask, labels and FP64 totals
+    TRY(label_current(s, (uint32_t*)s->labels.p, nullptr, nullptr, st.tot, true, false));
+    o.tot = (const double*)s->small.p;
+    if (s->two) {
+        TRY(gas_totals_queue(s));
+        o.tot2 = (const double*)s->small.p + 8;
+    }
+
+    // 2. on the device: nucleus labels, the bubble table, statistics and, with the criterion,
+    // the candidate pairs' merge test; then the read-back (one block does the tail)
+    BubbleTab t{};
+    bool do_pairs = false;
+    int pair_cap = 0;
+    if (n > 0) {
+        t = bubble_tab_view(s->btab.p, n);
+        HIPX(launch_bubble_table((const uint32_t*)s->labels.p, (const int64_t*)s->nodes.p, n, t,
+                                 (int32_t*)s->slots.p, fa, s->stream));
+        HIPX(launch_stats((const uint32_t*)s->labels.p, (const int32_t*)s->slots.p, t.anchors,
+                          t.count, t.sums, fa, s->stream));
+        if (with_criterion && n >= 2) {
+            do_pairs = true;
+            pair_cap = std::max(kStagePairs, s->pair_cap);
+            o.pairs = (const MergePair*)s->pair_buf.p;
+            o.ab = (const int32_t*)s->pair_ab.p;
+            o.res = (const MergeResult*)s->res_buf.p;
+            o.npairs = kStagePairs;
+        }
+        o.head = t.head;
+        o.comp = t.comp;
+        o.count = t.count;
+        o.sums = t.sums;
+        o.n = n;
+    }
+    // the source ledger of the last pass's bubbles, handed back to the nuclei that led them
+    o.owed = (const double*)s->ledger.p;
+    o.ledger_nb = s->ledger_nb;
+    // the merge groups are read where the host staged them (pinned memory)
+    HIPX(launch_pass_tail(s->q, s->p.storage, t, sd.group, s->p.film_max,
+                          (MergePair*)s->pair_buf.p, (int32_t*)s->pair_ab.p,
+                          (MergeResult*)s->res_buf.p, pair_cap, do_pairs ? 1 : 0, o,
+                          s->f[s->cur], (const uint32_t*)s->labels.p, fa, s->stream));
+    return SC_OK;
+}
+
+int pass_finish(sc_sim* s, bool with_criterion)
 {
 #pragma clang fp contract(off)
     const FieldArgs fa = field_args(s);
-    const int n = (int)s->rad.size();  // nucleus count (cen holds 3 values per nucleus)
-    hipEvent_t pe;
-    TRY(prof_begin(s, SC_KERNEL_TEST, &pe));
-
-    TRY(ensure(s, s->labels, sizeof(uint32_t) * (size_t)s->N));
-    // the totals' copy and the nucleus map below share one synchronization; the copy goes to
-    // the sim's own array, which outlives an early return
-    double* tot = s->pass_tot;
-    TRY(label_current(s, (uint32_t*)s->labels.p, nullptr, nullptr, tot, true));
+    const int n = (int)s->rad.size();
+    const Stage st = stage_view(s->stage, n);
+    const int ledger_nb = s->ledger_nb;
+    int pair_cap = (with_criterion && n >= 2) ? std::max(kStagePairs, s->pair_cap) : 0;
+    const BubbleTab t = n > 0 ? bubble_tab_view(s->btab.p, n) : BubbleTab{};
     s->have_labels = true;
-
-    // nucleus map: label at each nucleus node
-    s->comp.assign((size_t)n, 0u);
-    if (n > 0) {
-        TRY(ensure(s, s->nodes, sizeof(int64_t) * n + sizeof(uint32_t) * n));
-        int64_t* nodes_d = (int64_t*)s->nodes.p;
-        uint32_t* comp_d = (uint32_t*)((char*)s->nodes.p + sizeof(int64_t) * n);
-        HIPX(hipMemcpyAsync(nodes_d, s->nuc_node.data(), sizeof(int64_t) * n,
-                            hipMemcpyHostToDevice, s->stream));
-        HIPX(launch_gather_labels((const uint32_t*)s->labels.p, nodes_d, comp_d, n, s->N,
-                                  s->stream));
-        HIPX(hipMemcpyAsync(s->comp.data(), comp_d, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
-                            s->stream));
-    }
-    // the source ledger of the last pass's bubbles, handed back to the nuclei that led them
-    std::vector<double> owed_back((size_t)s->ledger_nb);
-    if (s->ledger_nb > 0)
-        HIPX(hipMemcpyAsync(owed_back.data(), s->ledger.p, sizeof(double) * owed_back.size(),
-                            hipMemcpyDeviceToHost, s->stream));
     HIPX(hipStreamSynchronize(s->stream));
-    for (size_t b = 0; b < owed_back.size(); ++b)
-        if (owed_back[b] != 0.0) s->owed_nuc[(size_t)s->ledger_lead[b]] += owed_back[b];
+
+    for (int b = 0; b < ledger_nb; ++b)
+        if (st.owed[b] != 0.0) s->owed_nuc[(size_t)s->ledger_lead[b]] += st.owed[b];
     s->ledger_nb = 0;
-    if (s->two) TRY(gas_totals_add(s, tot));
+    double tot[4];
+    for (int c = 0; c < 4; ++c) tot[c] = st.tot[c] + (s->two ? st.tot[4 + c] : 0.0);
+    for (int c = 0; c < 4; ++c) s->pass_tot[c] = tot[c];
     const bool finite = std::isfinite(tot[0]) && std::isfinite(tot[1]) &&
                         std::isfinite(tot[2]) && std::isfinite(tot[3]);
 
-    // bubbles: distinct nonzero labels held by nuclei, ascending
+    // 3. the host's registry from the nucleus labels: bubbles = distinct nonzero labels held by
+    // nuclei, ascending, each led by its smallest nucleus (the device table follows the same
+    // rules; its statistics are read by bubble index)
+    s->comp.assign(st.comp, st.comp + n);
     std::vector<uint32_t> distinct;
     for (int k = 0; k < n; ++k)
         if (s->comp[k]) distinct.push_back(s->comp[k]);
     std::sort(distinct.begin(), distinct.end());
     distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
     const int nb = (int)distinct.size();
+    if (n > 0 && st.head[0] != nb) {
+        s->latched = SC_E_STATE;
+        return fail(SC_E_STATE, "device bubble table disagrees with the nucleus labels");
+    }
     s->bub.assign((size_t)nb, sc_bubble{});
     s->bub_nuclei.assign((size_t)nb, std::vector<int>());
     for (int b = 0; b < nb; ++b) {
@@ -682,60 +869,25 @@ int test_pass(sc_sim* s, bool with_criterion)
         s->bub[b].n_nuclei++;
         s->bub_nuclei[b].push_back(k);
     }
+    for (int b = 0; b < nb; ++b) {
+        sc_bubble& B = s->bub[b];
+        const int64_t a0 = s->nuc_node[B.nucleus];
+        const int64_t anchor[3] = {a0 % s->p.nx, (a0 / s->p.nx) % s->p.ny,
+                                   a0 / ((int64_t)s->p.nx * s->p.ny)};
+        B.n = (int64_t)st.count[b];
+        for (int c = 0; c < 3; ++c)
+            B.centroid[c] = (double)anchor[c] + (double)(int64_t)st.sums[3 * b + c] / (double)B.n;
+        if (s->d == 2) {
+            B.centroid[2] = 0.0;
+            B.radius = std::sqrt((double)B.n / M_PI);
+        } else {
+            B.radius = std::cbrt(3.0 * (double)B.n / (4.0 * M_PI));
+        }
+    }
 
+    // 4. gas-node list of the bubbles the source feeds until the next pass
     s->list_count = 0;
     if (nb > 0) {
-        if (!s->slots_ready) {
-            TRY(ensure(s, s->slots, sizeof(int32_t) * (size_t)s->N));
-            HIPX(launch_fill_i32((int32_t*)s->slots.p, -1, s->N, s->stream));
-            s->slots_ready = true;
-        }
-        // per-bubble tables: labels, anchors, counts, offset sums, feed flags
-        const size_t off_anchor = sizeof(uint32_t) * nb;
-        const size_t off_count = ((off_anchor + sizeof(int32_t) * 3 * nb) + 255) & ~size_t(255);
-        const size_t off_sums = off_count + sizeof(unsigned long long) * nb;
-        const size_t off_feed = off_sums + sizeof(unsigned long long) * 3 * nb;
-        const size_t bytes = off_feed + sizeof(int32_t) * nb;
-        TRY(ensure(s, s->bub_tab, bytes));
-        char* base = (char*)s->bub_tab.p;
-        std::vector<int32_t> anchors((size_t)3 * nb);
-        for (int b = 0; b < nb; ++b) {
-            const int64_t a0 = s->nuc_node[s->bub[b].nucleus];
-            anchors[3 * b + 0] = (int32_t)(a0 % s->p.nx);
-            anchors[3 * b + 1] = (int32_t)((a0 / s->p.nx) % s->p.ny);
-            anchors[3 * b + 2] = (int32_t)(a0 / ((int64_t)s->p.nx * s->p.ny));
-        }
-        HIPX(hipMemcpyAsync(base, distinct.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice,
-                            s->stream));
-        HIPX(hipMemcpyAsync(base + off_anchor, anchors.data(), sizeof(int32_t) * 3 * nb,
-                            hipMemcpyHostToDevice, s->stream));
-        HIPX(launch_fill_u64((unsigned long long*)(base + off_count), 0ull, 4 * (int64_t)nb,
-                             s->stream));
-        HIPX(launch_set_slots((int32_t*)s->slots.p, (const uint32_t*)base, nb, 0, s->stream));
-        HIPX(launch_stats((const uint32_t*)s->labels.p, (const int32_t*)s->slots.p,
-                          (const int32_t*)(base + off_anchor), (unsigned long long*)(base + off_count),
-                          (unsigned long long*)(base + off_sums), fa, s->stream));
-        std::vector<unsigned long long> cnt((size_t)nb), sums((size_t)3 * nb);
-        HIPX(hipMemcpyAsync(cnt.data(), base + off_count, sizeof(unsigned long long) * nb,
-                            hipMemcpyDeviceToHost, s->stream));
-        HIPX(hipMemcpyAsync(sums.data(), base + off_sums, sizeof(unsigned long long) * 3 * nb,
-                            hipMemcpyDeviceToHost, s->stream));
-        HIPX(hipStreamSynchronize(s->stream));
-        for (int b = 0; b < nb; ++b) {
-            sc_bubble& B = s->bub[b];
-            B.n = (int64_t)cnt[b];
-            for (int c = 0; c < 3; ++c)
-                B.centroid[c] = (double)anchors[3 * b + c] +
-                                (double)(int64_t)sums[3 * b + c] / (double)B.n;
-            if (s->d == 2) {
-                B.centroid[2] = 0.0;
-                B.radius = std::sqrt((double)B.n / M_PI);
-            } else {
-                B.radius = std::cbrt(3.0 * (double)B.n / (4.0 * M_PI));
-            }
-        }
-
-        // gas-node list of the bubbles the source feeds until the next pass
         std::vector<int32_t> feed((size_t)nb, 0);
         int64_t cap = 0;
         if (s->rate > 0.0) {
@@ -746,7 +898,8 @@ int test_pass(sc_sim* s, bool with_criterion)
             }
         }
         if (cap > 0) {
-            HIPX(hipMemcpyAsync(base + off_feed, feed.data(), sizeof(int32_t) * nb,
+            TRY(ensure(s, s->bub_tab, sizeof(int32_t) * (size_t)nb));
+            HIPX(hipMemcpyAsync(s->bub_tab.p, feed.data(), sizeof(int32_t) * nb,
                                 hipMemcpyHostToDevice, s->stream));
             TRY(ensure(s, s->list_node, sizeof(uint32_t) * (size_t)cap));
             TRY(ensure(s, s->list_slot, sizeof(int32_t) * (size_t)cap));
@@ -755,7 +908,7 @@ int test_pass(sc_sim* s, bool with_criterion)
             HIPX(launch_fill_i32((int32_t*)cnt_d, 0, 1, s->stream));
             TRY(ensure(s, s->list_scan, sizeof(uint32_t) * (size_t)gas_list_scratch_words()));
             HIPX(launch_gas_list((const uint32_t*)s->labels.p, (const int32_t*)s->slots.p,
-                                 (const int32_t*)(base + off_feed), (uint32_t*)s->list_node.p,
+                                 (const int32_t*)s->bub_tab.p, (uint32_t*)s->list_node.p,
                                  (int32_t*)s->list_slot.p, cnt_d, (unsigned int*)s->list_scan.p,
                                  s->N, s->stream));
             unsigned int got = 0;
@@ -763,10 +916,10 @@ int test_pass(sc_sim* s, bool with_criterion)
             HIPX(hipStreamSynchronize(s->stream));
             s->list_count = got;
         }
-        TRY(ledger_setup(s, feed));
+        if (s->rate > 0.0) TRY(ledger_setup(s, feed));
     }
 
-    // topological merges: nuclei of one component join one group (smallest index leads)
+    // 5. topological merges: nuclei of one component join one group (smallest index leads)
     for (int b = 0; b < nb; ++b) {
         const int k0 = s->bub[b].nucleus;
         for (int k : s->bub_nuclei[b]) {
@@ -782,10 +935,52 @@ int test_pass(sc_sim* s, bool with_criterion)
         }
     }
 
-    // merge criterion on candidate pairs (pairs in label order, state of the pass start)
+    // 6. merge criterion on candidate pairs (pairs in label order, state of the pass start).
+    // The host forms the pairs exactly as before; the device has already walked every film of
+    // a superset of them, and each pair's result is taken from there after checking that the
+    // device formed the identical pair (centroid, offset and sample count).
     if (with_criterion && nb >= 2) {
-        std::vector<MergePair> pairs;
-        std::vector<std::pair<int, int>> who;
+        int found = st.head[1];
+        const MergePair* dev_pairs = st.pairs;
+        const int32_t* dev_ab = st.ab;
+        const MergeResult* dev_res = st.res;
+        std::vector<MergePair> more_pairs;
+        std::vector<int32_t> more_ab;
+        std::vector<MergeResult> more_res;
+        if (found > pair_cap) {  // grow the buffers and walk them all again on the device
+            s->pair_cap = found;
+            pair_cap = found;
+            TRY(ensure(s, s->pair_buf, sizeof(MergePair) * (size_t)pair_cap));
+            TRY(ensure(s, s->res_buf, sizeof(MergeResult) * (size_t)pair_cap));
+            TRY(ensure(s, s->pair_ab, sizeof(int32_t) * 2 * (size_t)pair_cap));
+            HIPX(launch_fill_i32(t.head + 1, 0, 1, s->stream));  // the pair count starts over
+            HIPX(launch_pairs(t, stage_view(s->stage_dev, n).group, s->d, s->p.film_max,
+                              (MergePair*)s->pair_buf.p, (int32_t*)s->pair_ab.p, pair_cap, fa,
+                              s->stream));
+            HIPX(launch_merge_counted(s->q, s->p.storage, s->f[s->cur],
+                                      (const uint32_t*)s->labels.p,
+                                      (const MergePair*)s->pair_buf.p,
+                                      (MergeResult*)s->res_buf.p, pair_cap, t.head + 1,
+                                      s->p.film_max, fa, s->stream));
+        }
+        if (found > kStagePairs) {
+            more_pairs.resize((size_t)found);
+            more_ab.resize(2 * (size_t)found);
+            more_res.resize((size_t)found);
+            HIPX(hipMemcpyAsync(more_pairs.data(), s->pair_buf.p, sizeof(MergePair) * found,
+                                hipMemcpyDeviceToHost, s->stream));
+            HIPX(hipMemcpyAsync(more_ab.data(), s->pair_ab.p, sizeof(int32_t) * 2 * found,
+                                hipMemcpyDeviceToHost, s->stream));
+            HIPX(hipMemcpyAsync(more_res.data(), s->res_buf.p, sizeof(MergeResult) * found,
+                                hipMemcpyDeviceToHost, s->stream));
+            HIPX(hipStreamSynchronize(s->stream));
+            dev_pairs = more_pairs.data();
+            dev_ab = more_ab.data();
+            dev_res = more_res.data();
+        }
+        std::map<std::pair<int, int>, int> at;
+        for (int k = 0; k < found; ++k) at[{dev_ab[2 * k], dev_ab[2 * k + 1]}] = k;
+        std::vector<std::pair<int, int>> fired;
         for (int a = 0; a < nb; ++a) {
             for (int b = a + 1; b < nb; ++b) {
                 const sc_bubble& A = s->bub[a];
@@ -800,37 +995,20 @@ int test_pass(sc_sim* s, bool with_criterion)
                 if (dist > A.radius + B.radius + (double)s->p.film_max) continue;
                 const int T = (int)std::ceil(dist);
                 if (T <= 0) continue;
-                MergePair mp;
-                for (int c = 0; c < 3; ++c) {
-                    mp.cen_a[c] = A.centroid[c];
-                    mp.dv[c] = dv[c];
+                const auto it = at.find({a, b});
+                bool same = it != at.end();
+                if (same) {
+                    const MergePair& dp = dev_pairs[it->second];
+                    same = dp.T == T && dp.label_a == A.label && dp.label_b == B.label;
+                    for (int c = 0; c < 3; ++c)
+                        same = same && dp.cen_a[c] == A.centroid[c] && dp.dv[c] == dv[c];
                 }
-                mp.label_a = A.label;
-                mp.label_b = B.label;
-                mp.T = T;
-                mp.pad = 0;
-                pairs.push_back(mp);
-                who.emplace_back(a, b);
-            }
-        }
-        const int np = (int)pairs.size();
-        if (np > 0) {
-            TRY(ensure(s, s->pair_buf, sizeof(MergePair) * np));
-            TRY(ensure(s, s->res_buf, sizeof(MergeResult) * np));
-            HIPX(hipMemcpyAsync(s->pair_buf.p, pairs.data(), sizeof(MergePair) * np,
-                                hipMemcpyHostToDevice, s->stream));
-            HIPX(launch_merge(s->q, s->p.storage, s->f[s->cur], (const uint32_t*)s->labels.p,
-                              (const MergePair*)s->pair_buf.p, (MergeResult*)s->res_buf.p, np,
-                              s->p.film_max, fa, s->stream));
-            std::vector<MergeResult> res((size_t)np);
-            HIPX(hipMemcpyAsync(res.data(), s->res_buf.p, sizeof(MergeResult) * np,
-                                hipMemcpyDeviceToHost, s->stream));
-            HIPX(hipStreamSynchronize(s->stream));
-            std::vector<std::pair<int, int>> fired;
-            for (int k = 0; k < np; ++k) {
-                if (!res[k].fired) continue;
-                const sc_bubble& A = s->bub[who[k].first];
-                const sc_bubble& B = s->bub[who[k].second];
+                if (!same) {
+                    s->latched = SC_E_STATE;
+                    return fail(SC_E_STATE, "device merge pair differs from the registry's");
+                }
+                const MergeResult& r = dev_res[it->second];
+                if (!r.fired) continue;
                 sc_merge_event e;
                 std::memset(&e, 0, sizeof(e));
                 e.step = s->t;
@@ -838,35 +1016,46 @@ int test_pass(sc_sim* s, bool with_criterion)
                 e.nucleus_b = B.nucleus;
                 e.label_a = A.label;
                 e.label_b = B.label;
-                e.film_node = res[k].film_node;
-                e.film_len = res[k].film_len;
-                e.lap_p = res[k].lap_p;
-                e.rho_film = res[k].rho_film;
+                e.film_node = r.film_node;
+                e.film_len = r.film_len;
+                e.lap_p = r.lap_p;
+                e.rho_film = r.rho_film;
                 s->events.push_back(e);
                 fired.emplace_back(A.nucleus, B.nucleus);
             }
-            // eta_m: 1 -> 0, applied after every pair was tested
-            for (auto& pr : fired) {
-                const int ra = uf_find(s->merge_parent, pr.first);
-                const int rb = uf_find(s->merge_parent, pr.second);
-                if (ra == rb) continue;
-                if (ra < rb) s->merge_parent[rb] = ra; else s->merge_parent[ra] = rb;
-            }
+        }
+        // eta_m: 1 -> 0, applied after every pair was tested
+        for (auto& pr : fired) {
+            const int ra = uf_find(s->merge_parent, pr.first);
+            const int rb = uf_find(s->merge_parent, pr.second);
+            if (ra == rb) continue;
+            if (ra < rb) s->merge_parent[rb] = ra; else s->merge_parent[ra] = rb;
+            s->group_dirty = true;
         }
     }
 
     if (s->p.barrier) TRY(build_owner(s, nb));
     if (nb > 0)  // slot map back to "no bubble" for the next pass
-        HIPX(launch_set_slots((int32_t*)s->slots.p, (const uint32_t*)s->bub_tab.p, nb, 1, s->stream));
+        HIPX(launch_set_slots((int32_t*)s->slots.p, t.distinct, nb, 1, s->stream));
 
     build_schedule(s, schedule_chunk_len(s));
-    TRY(upload_schedule(s));
-    TRY(prof_end(s, pe));
+    if (s->rate > 0.0) TRY(upload_schedule(s));
     if (!finite) {
         s->latched = SC_E_NUMERIC;
         return fail(SC_E_NUMERIC, "non-finite FP64 total at step " + std::to_string(s->t));
     }
     return SC_OK;
+}
+
+int test_pass(sc_sim* s, bool with_criterion)
+{
+    hipEvent_t pe;
+    TRY(prof_begin(s, SC_KERNEL_TEST, &pe));
+    TRY(pass_prepare(s, with_criterion));
+    TRY(pass_enqueue(s, with_criterion));
+    const int rc = pass_finish(s, with_criterion);
+    TRY(prof_end(s, pe));
+    return rc;
 }
 
 int validate(const sc_params* p)
@@ -943,8 +1132,10 @@ void release(sc_sim* s)
                       &s->u_out, &s->p_out, &s->lap_out, &s->partials, &s->small, &s->tmp64,
                       &s->mask8, &s->nodes, &s->list_node, &s->list_slot, &s->add_tab,
                       &s->pair_buf, &s->res_buf, &s->bub_tab, &s->owner, &s->owner2,
-                      &s->owner_ids, &s->frontier, &s->ledger, &s->list_scan})
+                      &s->owner_ids, &s->frontier, &s->ledger, &s->list_scan, &s->btab,
+                      &s->pair_ab})
         dev_free(s, b->p);
+    if (s->stage) (void)hipHostFree(s->stage);
     dev_free(s, s->f[0]);
     dev_free(s, s->f[1]);
     dev_free(s, s->fv[0]);
@@ -955,6 +1146,10 @@ void release(sc_sim* s)
         (void)hipEventDestroy(r.b);
     }
     for (auto e : s->pool) (void)hipEventDestroy(e);
+    for (auto& g : s->graph_exec)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& g : s->pass_exec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
 }
 
@@ -1132,6 +1327,14 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
         s->merge_parent[k] = k;
         s->topo_parent[k] = k;
     }
+    // the nucleus nodes live on the device for the test passes' bubble table
+    s->group_dirty = true;
+    if (n > 0) {
+        TRY(ensure(s, s->nodes, sizeof(int64_t) * (size_t)n));
+        HIPX(hipMemcpyAsync(s->nodes.p, s->nuc_node.data(), sizeof(int64_t) * n,
+                            hipMemcpyHostToDevice, s->stream));
+        HIPX(hipStreamSynchronize(s->stream));
+    }
     const InitArgs ia = init_args(s, s->p.rho_gas);
     const InitArgs va = init_args_gas(s, s->p.rho_vapour);  // bubbles hold the gas component
     for (int k = 0; k < n; ++k) {
@@ -1146,6 +1349,135 @@ int sc_seed_nuclei(sc_sim* s, int32_t n, const double* centre, const double* rad
     return test_pass(s, false);
 }
 
+// The step launches of one time step (the fused step, and the barrier fix-up if any frontier).
+static int launch_one_step(sc_sim* s, const StepArgs& a, int c)
+{
+    if (s->two)
+        HIPX(launch_step2c(s->q, s->p.storage, s->f[c], s->fv[c], s->f[c ^ 1], s->fv[c ^ 1],
+                           step2c_args(s), s->shape, s->stream));
+    else
+        HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[c], s->f[c ^ 1], a, s->shape,
+                         s->stream));
+    if (s->p.barrier && s->frontier_count > 0)
+        HIPX(launch_barrier_fix(s->q, s->p.storage, s->compute, s->f[c], s->f[c ^ 1], a,
+                                (const uint32_t*)s->frontier.p, s->frontier_count, s->stream));
+    return SC_OK;
+}
+
+// A K-step block runs as one graph when its launches are the same every block: a box small
+// enough that launching dominates (N <= 2^22 nodes), no barrier fix-up, and no source launch in
+// the block.  The block starts right after a test pass (t % K == 0, schedule position 0).
+static bool block_graph_ok(const sc_sim* s, int K, int left)
+{
+    if (!s->graphs || K <= 0 || left < K || s->t % K != 0 || s->N > ((int64_t)1 << 22))
+        return false;
+    if (s->p.barrier && s->frontier_count > 0) return false;
+    if (s->chunk_pos != 0 || s->chunk_len < K) return false;
+    if (s->list_count > 0)
+        for (int k = 0; k < K; ++k)
+            if (s->step_active[(size_t)k]) return false;
+    return true;
+}
+
+// Launches the K-step block from buffer parity s->cur, capturing it first if its arguments
+// changed since the last capture.
+static int run_block_graph(sc_sim* s, const StepArgs& a, int K)
+{
+    const int c0 = s->cur;
+    std::vector<char> key(sizeof(StepArgs) + sizeof(Step2cArgs) + sizeof(StepShape) +
+                          6 * sizeof(void*) + sizeof(int));
+    {
+        char* k = key.data();
+        const Step2cArgs a2 = step2c_args(s);
+        const void* ptrs[6] = {s->f[0], s->f[1], s->fv[0], s->fv[1], (void*)s->stream,
+                           s->frontier.p};
+        std::memcpy(k, &a, sizeof(a)); k += sizeof(a);
+        std::memcpy(k, &a2, sizeof(a2)); k += sizeof(a2);
+        std::memcpy(k, &s->shape, sizeof(s->shape)); k += sizeof(s->shape);
+        std::memcpy(k, ptrs, sizeof(ptrs)); k += sizeof(ptrs);
+        std::memcpy(k, &K, sizeof(K));
+    }
+    if (!s->graph_exec[c0] || s->graph_key[c0] != key) {
+        if (s->graph_exec[c0]) {
+            HIPX(hipGraphExecDestroy(s->graph_exec[c0]));
+            s->graph_exec[c0] = nullptr;
+        }
+        HIPX(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        int rc = SC_OK;
+        int c = c0;
+        for (int k = 0; k < K && rc == SC_OK; ++k, c ^= 1) rc = launch_one_step(s, a, c);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(s->stream, &g);
+        if (rc != SC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return device_fail(s, e, "hipStreamEndCapture");
+        const hipError_t ei = hipGraphInstantiate(&s->graph_exec[c0], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            s->graph_exec[c0] = nullptr;
+            return device_fail(s, ei, "hipGraphInstantiate");
+        }
+        s->graph_key[c0] = key;
+    }
+    hipEvent_t pe;
+    TRY(prof_begin(s, SC_KERNEL_STEP, &pe));
+    if (s->prof) s->recs.back().launches = K;
+    HIPX(hipGraphLaunch(s->graph_exec[c0], s->stream));
+    TRY(prof_end(s, pe));
+    return SC_OK;
+}
+
+// The device part of the test pass after a graph-run block, itself as a graph: captured from
+// pass_enqueue and valid while the buffers and arguments it captured stay the same.
+static int run_pass_graph(sc_sim* s)
+{
+    const int c0 = s->cur;
+    const FieldArgs fa = field_args(s);
+    const int n = (int)s->rad.size();
+    const int meta[6] = {n, s->pair_cap, s->two ? 1 : 0, c0, s->p.film_max, s->d};
+    const void* ptrs[16] = {s->labels.p, s->parent.p, s->small.p, s->partials.p, s->slots.p,
+                            s->btab.p, (void*)s->stage_dev, s->pair_buf.p, s->res_buf.p, s->pair_ab.p,
+                            s->nodes.p, (void*)s->stage, s->f[c0], s->fv[c0],
+                            (void*)s->stream, nullptr};
+    std::vector<char> key(sizeof(fa) + sizeof(meta) + sizeof(ptrs));
+    std::memcpy(key.data(), &fa, sizeof(fa));
+    std::memcpy(key.data() + sizeof(fa), meta, sizeof(meta));
+    std::memcpy(key.data() + sizeof(fa) + sizeof(meta), ptrs, sizeof(ptrs));
+    if (!s->pass_exec[c0] || s->pass_key[c0] != key) {
+        if (s->pass_exec[c0]) {
+            HIPX(hipGraphExecDestroy(s->pass_exec[c0]));
+            s->pass_exec[c0] = nullptr;
+        }
+        HIPX(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = pass_enqueue(s, true);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(s->stream, &g);
+        if (rc != SC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return device_fail(s, e, "hipStreamEndCapture");
+        const hipError_t ei = hipGraphInstantiate(&s->pass_exec[c0], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            s->pass_exec[c0] = nullptr;
+            return device_fail(s, ei, "hipGraphInstantiate");
+        }
+        s->pass_key[c0] = key;
+    }
+    HIPX(hipGraphLaunch(s->pass_exec[c0], s->stream));
+    return SC_OK;
+}
+
+int sc_step_graphs(sc_sim* s, int32_t enable)
+{
+    TRY(check_usable(s));
+    s->graphs = enable != 0;
+    return SC_OK;
+}
+
 int sc_step(sc_sim* s, int32_t nsteps)
 {
     TRY(check_usable(s));
@@ -1154,18 +1486,37 @@ int sc_step(sc_sim* s, int32_t nsteps)
     const FieldArgs fa = field_args(s);
     const int K = s->p.test_every;
     for (int it = 0; it < nsteps; ++it) {
+        if (block_graph_ok(s, K, nsteps - it)) {
+            // a whole K-step block without source launches: one graph, then the bookkeeping
+            // the per-step loop below does, and the test pass
+            TRY(run_block_graph(s, a, K));
+            if (K & 1) s->cur ^= 1;
+            for (int k = 0; k < K; ++k) {
+                if (!s->rem.empty() && s->chunk_len > 0) {
+                    const size_t n = s->rem.size();
+                    std::copy(s->rem_host.begin() + s->chunk_pos * n,
+                              s->rem_host.begin() + (s->chunk_pos + 1) * n, s->rem.begin());
+                }
+                s->chunk_pos++;
+                s->t += 1;
+            }
+            it += K - 1;
+            // the pass's device part as a graph too, unless a ledger is to be read back
+            hipEvent_t pe;
+            TRY(prof_begin(s, SC_KERNEL_TEST, &pe));
+            TRY(pass_prepare(s, true));
+            if (s->ledger_nb == 0)
+                TRY(run_pass_graph(s));
+            else
+                TRY(pass_enqueue(s, true));
+            const int rc = pass_finish(s, true);
+            TRY(prof_end(s, pe));
+            TRY(rc);
+            continue;
+        }
         hipEvent_t pe;
         TRY(prof_begin(s, SC_KERNEL_STEP, &pe));
-        if (s->two)
-            HIPX(launch_step2c(s->q, s->p.storage, s->f[s->cur], s->fv[s->cur], s->f[s->cur ^ 1],
-                               s->fv[s->cur ^ 1], step2c_args(s), s->shape, s->stream));
-        else
-            HIPX(launch_step(s->q, s->p.storage, s->compute, s->f[s->cur], s->f[s->cur ^ 1], a,
-                             s->shape, s->stream));
-        if (s->p.barrier && s->frontier_count > 0)
-            HIPX(launch_barrier_fix(s->q, s->p.storage, s->compute, s->f[s->cur],
-                                    s->f[s->cur ^ 1], a, (const uint32_t*)s->frontier.p,
-                                    s->frontier_count, s->stream));
+        TRY(launch_one_step(s, a, s->cur));
         TRY(prof_end(s, pe));
         s->cur ^= 1;
         // blowing-agent source after streaming
@@ -1749,7 +2100,7 @@ int sc_profile_read(sc_sim* s, int32_t cls, double* ms, int64_t* launches)
         float e = 0.0f;
         HIPX(hipEventElapsedTime(&e, r.a, r.b));
         tot += e;
-        ++cnt;
+        cnt += r.launches;
     }
     if (ms) *ms = tot;
     if (launches) *launches = cnt;

@@ -161,9 +161,74 @@ struct MergeResult {
     double lap_p;
     double rho_film;
 };
-hipError_t launch_merge(int q, int storage, const void* f, const uint32_t* labels,
-                        const MergePair* pairs_d, MergeResult* res_d, int npairs, int film_max,
-                        const FieldArgs& a, hipStream_t st);
+
+// Bubble table of a test pass, built on the device so that the pass needs one synchronization:
+// the label at every nucleus node, the distinct nonzero labels in ascending order (the bubbles),
+// the lead (smallest) nucleus of each with its node's coordinates (the centroid anchor), the slot
+// of each bubble's root in slot_of_root, and zeroed statistics for k_stats.  One buffer of
+// bubble_tab_bytes(n) bytes holds every table; head[0] = nb, head[1] = candidate pairs found.
+struct BubbleTab {
+    int32_t* head;
+    uint32_t* comp;             // [n]
+    uint32_t* distinct;         // [n], nb used
+    int32_t* lead;              // [n]
+    int32_t* first;             // [n] scratch: 1 for the smallest nucleus of each label
+    int32_t* anchors;           // [3n]
+    unsigned long long* count;  // [n]
+    unsigned long long* sums;   // [3n]
+    double* cen;                // [3n]
+    double* rad;                // [n]
+};
+size_t bubble_tab_bytes(int n);
+BubbleTab bubble_tab_view(void* base, int n);
+hipError_t launch_bubble_table(const uint32_t* labels, const int64_t* nuc_node, int n,
+                               const BubbleTab& t, int32_t* slot_of_root, const FieldArgs& a,
+                               hipStream_t st);
+// Candidate pairs of the merge test: FP64 centroids and radii formed as the host forms them,
+// then every pair a < b of different merge groups (group[k]: representative of nucleus k) within
+// radius_a + radius_b + film_max + 1e-6 (a superset of the host's exact test), compacted into
+// pairs[] with the bubble indices in ab[2k], ab[2k + 1] (order unspecified); head[1] = the number
+// found, which may exceed cap (then the first cap are written).
+hipError_t launch_pairs(const BubbleTab& t, const int32_t* group, int dim, int film_max,
+                        MergePair* pairs, int32_t* ab, int cap, const FieldArgs& a,
+                        hipStream_t st);
+// Everything a test pass reads back, gathered by one kernel into pinned host memory (dst_*,
+// device-accessible addresses of it): one write over the bus instead of a copy per table.
+struct StageOut {
+    const double* tot;          // [4] (and [4] gas-component totals when tot2 != nullptr)
+    const double* tot2;
+    const int32_t* head;        // [16]
+    const uint32_t* comp;       // [n]
+    const unsigned long long* count;  // [n]
+    const unsigned long long* sums;   // [3n]
+    const double* owed;         // [ledger_nb]
+    const MergePair* pairs;     // [npairs]
+    const int32_t* ab;          // [2 npairs]
+    const MergeResult* res;     // [npairs]
+    double* dst_tot;            // [8]
+    int32_t* dst_head;
+    uint32_t* dst_comp;
+    unsigned long long* dst_count;
+    unsigned long long* dst_sums;
+    double* dst_owed;
+    MergePair* dst_pairs;
+    int32_t* dst_ab;
+    MergeResult* dst_res;
+    int n, ledger_nb, npairs;
+};
+hipError_t launch_stage_out(const StageOut& o, hipStream_t st);
+
+// The tail of a test pass in one block: with do_pairs, the candidate pairs (as launch_pairs)
+// and their merge test; then the read-back (as launch_stage_out).
+hipError_t launch_pass_tail(int q, int storage, const BubbleTab& t, const int32_t* group,
+                            int film_max, MergePair* pairs, int32_t* ab, MergeResult* res,
+                            int cap, int do_pairs, const StageOut& o, const void* f,
+                            const uint32_t* labels, const FieldArgs& a, hipStream_t st);
+// k_merge over the first min(*count_d, cap) pairs.
+hipError_t launch_merge_counted(int q, int storage, const void* f, const uint32_t* labels,
+                                const MergePair* pairs_d, MergeResult* res_d, int cap,
+                                const int32_t* count_d, int film_max, const FieldArgs& a,
+                                hipStream_t st);
 
 // Film geometry of a bubble pair (h and the line count behind R_d): lines parallel to the
 // centroid segment, at offsets i n1 + j n2 (i^2 + j^2 <= K^2), walked like the merge test.

@@ -240,11 +240,13 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
 
 // ------------------------------------------------------------------------------------------
 // D3Q19, software-pipelined: the loads of plane z+2 are issued before plane z is collided, so a
-// wave keeps a plane of loads in flight through its collision and stores.  Ring nodes are spread
-// evenly over the waves of the block (ring node r -> wave r % W, lane r / W), so no wave carries
-// the whole ring.  Iteration z reads psi slots of planes z-1, z, z+1 and writes plane z+2's slot
+// wave keeps a plane of loads in flight through its collision and stores.  Ring nodes go to the
+// first threads of the block, as in k_step3d: a wave executes the ring's loads whether one lane
+// or all 64 need them, so packing the ring into as few waves as possible keeps the instruction
+// count down.  Iteration z reads psi slots of planes z-1, z, z+1 and writes plane z+2's slot
 // after its collision; the one barrier at the end of the iteration separates writers from readers
-// (plane z-2's slot, overwritten now, was last read before the previous barrier).
+// (plane z-2's slot, overwritten now, was last read before the previous barrier).  Stores are
+// non-temporal.
 // ------------------------------------------------------------------------------------------
 template <typename S, typename A, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ src,
@@ -252,7 +254,6 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
                                                         StepGrid grid)
 {
     using L = lat<19>;
-    constexpr int NW = (TX * TY) / 64;
     __shared__ A ps[4][TY + 2][TX + 2];
     const Coef<A> c = coef_of(a, A());
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -272,7 +273,7 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
     const int ym = wrap_once(y - 1, ny), yp = wrap_once(y + 1, ny);
 
     const int nring = 2 * (wx + 2) + 2 * wy;
-    const int r = (t & 63) * NW + (t >> 6);
+    const int r = t;
     const bool ring = r < nring;
     int hlx, hly;
     if (r < wx + 2) {
@@ -338,8 +339,8 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
                 },
                 fx, fy, fz);
             const A gp = -c.G * pc;
-            collide_store<19, A, S>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
-                                    gp * fx, gp * fy, gp * fz, c);
+            collide_store<19, A, S, true>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
+                                          gp * fx, gp * fy, gp * fz, c);
         }
         A dpre = (A)0;
         if (more) {

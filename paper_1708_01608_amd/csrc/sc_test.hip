@@ -451,7 +451,7 @@ __device__ __forceinline__ bool local_link(int lx, int ly, int lz, int x, int y,
 }
 
 template <int Q>
-__global__ void __launch_bounds__(256) k_union_local(uint32_t* parent, FieldArgs a)
+__global__ void __launch_bounds__(1024) k_union_local(uint32_t* parent, FieldArgs a)
 {
     using L = lat<Q>;
     using T = UnionTile<Q>;
@@ -681,71 +681,130 @@ __device__ __forceinline__ int64_t walk_node(const MergePair& pr, int k, const F
     return idx3(x, y, z, a.nx, a.ny);
 }
 
+// One wave tests one pair: the lanes take consecutive samples of the walk, so the walk's node
+// arithmetic and label loads run side by side instead of one after another.  Repeats of the
+// previous sample's node are dropped and positions counted over the kept samples, exactly as a
+// sequential walk would; the densest film node is the first of the maxima in walk order, and the
+// Laplacian's terms are summed by lane 0 in direction order.  Every lane of the wave must call
+// this; all of them return the same result.
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 template <int Q, typename S>
-__global__ void k_merge(const S* f, const uint32_t* labels, const MergePair* pairs,
-                        MergeResult* res, int npairs, int film_max, FieldArgs a)
+__device__ MergeResult merge_pair_wave(const MergePair& pr, const uint32_t* labels, const S* f,
+                                       int film_max, const FieldArgs& a)
 {
     using L = lat<Q>;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
-    const MergePair pr = pairs[p];
+    const int lane = (int)(threadIdx.x & 63);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int nk = pr.T + 1;
     MergeResult r;
     r.fired = 0; r.film_len = -1; r.film_node = -1; r.lap_p = 0.0; r.rho_film = 0.0;
-    // walk (consecutive repeats dropped): last node of a, then first node of b after it
-    int sa = -1, sb = -1, pos = -1;
-    int64_t prev = -1;
-    for (int k = 0; k <= pr.T; ++k) {
-        const int64_t nd = walk_node<Q>(pr, k, a);
-        if (nd == prev) continue;
-        prev = nd;
-        ++pos;
-        if (labels[nd] == pr.label_a) sa = pos;
-    }
-    if (sa >= 0) {
-        prev = -1; pos = -1;
-        for (int k = 0; k <= pr.T && sb < 0; ++k) {
-            const int64_t nd = walk_node<Q>(pr, k, a);
-            if (nd == prev) continue;
-            prev = nd;
-            ++pos;
-            if (pos > sa && labels[nd] == pr.label_b) sb = pos;
+    // Visits the kept samples chunk by chunk: fn(kept, pos, node) per lane, with the chunk's
+    // lanes in walk order; fn returns false (wave-uniformly) to stop.
+    auto walk = [&](auto fn) {
+        int64_t carry_node = -1;
+        int carry_pos = -1;
+        for (int k0 = 0; k0 < nk; k0 += 64) {
+            const int k = k0 + lane;
+            const bool in = k < nk;
+            const int64_t nd = in ? walk_node<Q>(pr, k, a) : (int64_t)-2;
+            int64_t prev = __shfl_up(nd, 1, 64);
+            if (lane == 0) prev = carry_node;
+            const bool keep = in && nd != prev;
+            const unsigned long long km = __ballot(keep);
+            const int pos = carry_pos + __popcll(km & below) + 1;
+            if (!fn(keep, pos, nd)) return;
+            carry_pos += __popcll(km);
+            const int last = min(63, nk - 1 - k0);
+            carry_node = __shfl(nd, last, 64);
         }
-    }
+    };
+    // last node of a; then the first node of b after it
+    int sa = -1;
+    walk([&](bool keep, int pos, int64_t nd) {
+        const int c = (keep && labels[nd] == pr.label_a) ? pos : -1;
+        sa = max(sa, wave_max_i(c));
+        return true;
+    });
+    if (sa < 0) return r;
+    int sb = -1;
+    walk([&](bool keep, int pos, int64_t nd) {
+        const int c = (keep && pos > sa && labels[nd] == pr.label_b) ? pos : 0x7fffffff;
+        const int m = wave_min_i(c);
+        if (m != 0x7fffffff) sb = m;
+        return sb < 0;
+    });
     const int len = sb - sa - 1;
-    if (sa >= 0 && sb >= 0 && len >= 1 && len <= film_max) {
-        // film run: positions sa+1 .. sb-1; liquid only; densest node first on ties
-        bool clean = true;
-        int64_t cstar = -1;
-        double best = 0.0;
-        prev = -1; pos = -1;
-        for (int k = 0; k <= pr.T; ++k) {
-            const int64_t nd = walk_node<Q>(pr, k, a);
-            if (nd == prev) continue;
-            prev = nd;
-            ++pos;
-            if (pos <= sa || pos >= sb) continue;
-            if (labels[nd] != 0) clean = false;
-            const double rho = rho_d<Q, S>(f, nd, a);
-            if (cstar < 0 || rho > best) { cstar = nd; best = rho; }
-        }
-        if (clean) {
-            int x, y, z;
-            coords3(cstar, a.nx, a.ny, x, y, z);
-            const double pc = pressure_at<Q, S>(f, cstar, a);
-            double acc = 0.0;
-            for (int i = 1; i < Q; ++i) {
-                const int64_t m = shifted<Q>(x, y, z, i, +1, a);
-                acc += L::wd[i] * (pressure_at<Q, S>(f, m, a) - pc);
+    if (sb < 0 || len < 1 || len > film_max) return r;
+    // film run: positions sa+1 .. sb-1; liquid only; densest node first on ties
+    bool clean = true;
+    int64_t cstar = -1;
+    double best = 0.0;
+    walk([&](bool keep, int pos, int64_t nd) {
+        const bool film = keep && pos > sa && pos < sb;
+        if (__ballot(film && labels[nd] != 0)) clean = false;
+        const double rho = film ? rho_d<Q, S>(f, nd, a) : -INFINITY;
+        const double m = wave_max_d(rho);
+        const unsigned long long at = __ballot(film && rho == m);
+        if (at) {
+            const int l0 = __ffsll(at) - 1;
+            const int64_t node = __shfl(nd, l0, 64);
+            if (cstar < 0 || m > best) {
+                cstar = node;
+                best = m;
             }
-            const double lap = 6.0 * acc;
-            r.film_len = len;
-            r.film_node = cstar;
-            r.lap_p = lap;
-            r.rho_film = best;
-            r.fired = lap >= 0.0 ? 1 : 0;
         }
+        return true;
+    });
+    if (!clean) return r;
+    int x, y, z;
+    coords3(cstar, a.nx, a.ny, x, y, z);
+    const double pc = pressure_at<Q, S>(f, cstar, a);
+    double term = 0.0;
+    if (lane >= 1 && lane < Q) {
+        const int64_t m = shifted<Q>(x, y, z, lane, +1, a);
+        term = L::wd[lane] * (pressure_at<Q, S>(f, m, a) - pc);
     }
-    res[p] = r;
+    double acc = 0.0;
+    for (int i = 1; i < Q; ++i) acc += __shfl(term, i, 64);
+    const double lap = 6.0 * acc;
+    r.film_len = len;
+    r.film_node = cstar;
+    r.lap_p = lap;
+    r.rho_film = best;
+    r.fired = lap >= 0.0 ? 1 : 0;
+    return r;
+}
+
+// One wave (one block of 64) per candidate pair, over the first min(*count_d, npairs) pairs.
+template <int Q, typename S>
+__global__ void __launch_bounds__(64) k_merge(const S* f, const uint32_t* labels,
+                                              const MergePair* pairs, MergeResult* res,
+                                              int npairs, const int32_t* count_d, int film_max,
+                                              FieldArgs a)
+{
+    const int p = blockIdx.x;
+    if (count_d && *count_d < npairs) npairs = *count_d;
+    if (p >= npairs) return;
+    const MergeResult r = merge_pair_wave<Q, S>(pairs[p], labels, f, film_max, a);
+    if (threadIdx.x == 0) res[p] = r;
 }
 
 // ---- blowing-agent source (Sec. 3): f_i(x) += w_i dm_b / n_b on the gas nodes of bubble b ----
@@ -1115,7 +1174,7 @@ static hipError_t launch_union_tiled(uint32_t* parent, const FieldArgs& a, hipSt
     const int64_t tiles = (int64_t)((a.nx + T::TX - 1) / T::TX) * ((a.ny + T::TY - 1) / T::TY) *
                           ((a.nz + T::TZ - 1) / T::TZ);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_union_local<Q>), dim3((unsigned)tiles), dim3(256), 0, st, parent, a);
+    hipLaunchKernelGGL((k_union_local<Q>), dim3((unsigned)tiles), dim3(1024), 0, st, parent, a);
     hipLaunchKernelGGL((k_union_cross<Q>), grid_for(a.N), dim3(256), 0, st, parent, a);
     return hipGetLastError();
 }
@@ -1177,15 +1236,240 @@ hipError_t launch_gas_list(const uint32_t* labels, const int32_t* slot_of_root,
     return hipGetLastError();
 }
 
-hipError_t launch_merge(int q, int storage, const void* f, const uint32_t* labels,
-                        const MergePair* pairs_d, MergeResult* res_d, int npairs, int film_max,
-                        const FieldArgs& a, hipStream_t st)
+hipError_t launch_merge_counted(int q, int storage, const void* f, const uint32_t* labels,
+                                const MergePair* pairs_d, MergeResult* res_d, int cap,
+                                const int32_t* count_d, int film_max, const FieldArgs& a,
+                                hipStream_t st)
 {
-    if (npairs <= 0) return hipSuccess;
-    const dim3 g((npairs + 63) / 64);
+    if (cap <= 0) return hipSuccess;
+    const dim3 g((unsigned)cap);
     SC_DISPATCH(q, storage,
                 hipLaunchKernelGGL((k_merge<QQ, SS>), g, dim3(64), 0, st, (const SS*)f, labels,
-                                   pairs_d, res_d, npairs, film_max, a));
+                                   pairs_d, res_d, cap, count_d, film_max, a));
+    return hipGetLastError();
+}
+
+// ---- read-back of a test pass ----------------------------------------------------------------
+__device__ void stage_out_body(const StageOut& o)
+{
+    const int t = threadIdx.x;
+    if (t < 4) o.dst_tot[t] = o.tot[t];
+    if (t >= 4 && t < 8 && o.tot2) o.dst_tot[t] = o.tot2[t - 4];
+    if (o.head && t < 16) o.dst_head[t] = o.head[t];
+    for (int k = t; k < o.n; k += blockDim.x) {
+        o.dst_comp[k] = o.comp[k];
+        o.dst_count[k] = o.count[k];
+        o.dst_sums[3 * k + 0] = o.sums[3 * k + 0];
+        o.dst_sums[3 * k + 1] = o.sums[3 * k + 1];
+        o.dst_sums[3 * k + 2] = o.sums[3 * k + 2];
+    }
+    for (int k = t; k < o.ledger_nb; k += blockDim.x) o.dst_owed[k] = o.owed[k];
+    for (int k = t; k < o.npairs; k += blockDim.x) {
+        o.dst_pairs[k] = o.pairs[k];
+        o.dst_ab[2 * k] = o.ab[2 * k];
+        o.dst_ab[2 * k + 1] = o.ab[2 * k + 1];
+        o.dst_res[k] = o.res[k];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_stage_out(StageOut o) { stage_out_body(o); }
+
+hipError_t launch_stage_out(const StageOut& o, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stage_out, dim3(1), dim3(256), 0, st, o);
+    return hipGetLastError();
+}
+
+// ---- device bubble table and candidate pairs --------------------------------------------------
+static size_t tab_align(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t bubble_tab_bytes(int n)
+{
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    return tab_align(64) + tab_align(4 * m) * 4 + tab_align(12 * m) + tab_align(8 * m) +
+           tab_align(24 * m) + tab_align(24 * m) + tab_align(8 * m);
+}
+
+BubbleTab bubble_tab_view(void* base, int n)
+{
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    char* p = (char*)base;
+    BubbleTab t;
+    t.head = (int32_t*)p; p += tab_align(64);
+    t.comp = (uint32_t*)p; p += tab_align(4 * m);
+    t.distinct = (uint32_t*)p; p += tab_align(4 * m);
+    t.lead = (int32_t*)p; p += tab_align(4 * m);
+    t.first = (int32_t*)p; p += tab_align(4 * m);
+    t.anchors = (int32_t*)p; p += tab_align(12 * m);
+    t.count = (unsigned long long*)p; p += tab_align(8 * m);
+    t.sums = (unsigned long long*)p; p += tab_align(24 * m);
+    t.cen = (double*)p; p += tab_align(24 * m);
+    t.rad = (double*)p;
+    return t;
+}
+
+// One block.  A bubble is a distinct nonzero label held by a nucleus node; its slot is the rank
+// of its label among them and its lead nucleus the smallest index holding it (both O(n^2 / 1024)
+// comparisons, a few microseconds for hundreds of nuclei).
+__global__ void __launch_bounds__(1024) k_bubble_table(const uint32_t* labels,
+                                                       const int64_t* nuc_node, int n, int64_t N,
+                                                       BubbleTab t, int32_t* slot_of_root, int nx,
+                                                       int ny)
+{
+    __shared__ int nb;
+    if (threadIdx.x == 0) nb = 0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const int64_t nd = nuc_node[k];
+        t.comp[k] = (nd >= 0 && nd < N) ? labels[nd] : 0u;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const uint32_t c = t.comp[k];
+        int first = c != 0u;
+        for (int j = 0; j < k && first; ++j)
+            if (t.comp[j] == c) first = 0;
+        t.first[k] = first;
+        if (first) atomicAdd(&nb, 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        if (!t.first[k]) continue;
+        const uint32_t c = t.comp[k];
+        int b = 0;
+        for (int j = 0; j < n; ++j)
+            if (t.first[j] && t.comp[j] < c) ++b;
+        t.distinct[b] = c;
+        t.lead[b] = k;
+        const int64_t a0 = nuc_node[k];
+        t.anchors[3 * b + 0] = (int32_t)(a0 % nx);
+        t.anchors[3 * b + 1] = (int32_t)((a0 / nx) % ny);
+        t.anchors[3 * b + 2] = (int32_t)(a0 / ((int64_t)nx * ny));
+        t.count[b] = 0ull;
+        t.sums[3 * b + 0] = 0ull;
+        t.sums[3 * b + 1] = 0ull;
+        t.sums[3 * b + 2] = 0ull;
+        slot_of_root[c - 1] = b;
+    }
+    if (threadIdx.x == 0) {
+        t.head[0] = nb;
+        t.head[1] = 0;
+    }
+}
+
+hipError_t launch_bubble_table(const uint32_t* labels, const int64_t* nuc_node, int n,
+                               const BubbleTab& t, int32_t* slot_of_root, const FieldArgs& a,
+                               hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bubble_table, dim3(1), dim3(1024), 0, st, labels, nuc_node, n, a.N, t,
+                       slot_of_root, a.nx, a.ny);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double min_image_d(double d, int n)
+{
+#pragma clang fp contract(off)
+    return d - n * floor(d / n + 0.5);
+}
+
+// One block: centroid = anchor + (sum of integer offsets) / n and the equal-area (2D) or
+// equal-volume (3D) radius, in the host's operation order; then the candidate pairs.
+__device__ void find_pairs(const BubbleTab& t, const int32_t* group, int dim, int film_max,
+                           MergePair* pairs, int32_t* ab, int cap, int nx, int ny, int nz)
+{
+#pragma clang fp contract(off)
+    const int nb = t.head[0];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double n = (double)t.count[b];
+        for (int c = 0; c < 3; ++c)
+            t.cen[3 * b + c] = (double)t.anchors[3 * b + c] + (double)(long long)t.sums[3 * b + c] / n;
+        if (dim == 2) {
+            t.cen[3 * b + 2] = 0.0;
+            t.rad[b] = sqrt(n / M_PI);
+        } else {
+            t.rad[b] = cbrt(3.0 * n / (4.0 * M_PI));
+        }
+    }
+    __syncthreads();
+    const int64_t total = (int64_t)nb * nb;
+    for (int64_t p = threadIdx.x; p < total; p += blockDim.x) {
+        const int a = (int)(p / nb), b = (int)(p % nb);
+        if (b <= a) continue;
+        if (group[t.lead[a]] == group[t.lead[b]]) continue;
+        double dv[3];
+        dv[0] = min_image_d(t.cen[3 * b + 0] - t.cen[3 * a + 0], nx);
+        dv[1] = min_image_d(t.cen[3 * b + 1] - t.cen[3 * a + 1], ny);
+        dv[2] = (dim == 3) ? min_image_d(t.cen[3 * b + 2] - t.cen[3 * a + 2], nz) : 0.0;
+        const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        if (dist > t.rad[a] + t.rad[b] + (double)film_max + 1e-6) continue;
+        const int T = (int)ceil(dist);
+        if (T <= 0) continue;
+        const int k = atomicAdd(&t.head[1], 1);
+        if (k >= cap) continue;
+        MergePair mp;
+        for (int c = 0; c < 3; ++c) {
+            mp.cen_a[c] = t.cen[3 * a + c];
+            mp.dv[c] = dv[c];
+        }
+        mp.label_a = t.distinct[a];
+        mp.label_b = t.distinct[b];
+        mp.T = T;
+        mp.pad = 0;
+        pairs[k] = mp;
+        ab[2 * k] = a;
+        ab[2 * k + 1] = b;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_pairs(BubbleTab t, const int32_t* group, int dim,
+                                                int film_max, MergePair* pairs, int32_t* ab,
+                                                int cap, int nx, int ny, int nz)
+{
+    find_pairs(t, group, dim, film_max, pairs, ab, cap, nx, ny, nz);
+}
+
+hipError_t launch_pairs(const BubbleTab& t, const int32_t* group, int dim, int film_max,
+                        MergePair* pairs, int32_t* ab, int cap, const FieldArgs& a,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pairs, dim3(1), dim3(1024), 0, st, t, group, dim, film_max, pairs, ab,
+                       cap, a.nx, a.ny, a.nz);
+    return hipGetLastError();
+}
+
+// The tail of a test pass in one block: candidate pairs, their merge test (one wave per pair,
+// sixteen at a time) and the read-back into pinned host memory.
+template <int Q, typename S>
+__global__ void __launch_bounds__(1024) k_pass_tail(BubbleTab t, const int32_t* group, int dim,
+                                                    int film_max, MergePair* pairs, int32_t* ab,
+                                                    MergeResult* res, int cap, int do_pairs,
+                                                    StageOut o, const S* f,
+                                                    const uint32_t* labels, FieldArgs a)
+{
+    if (do_pairs) {
+        find_pairs(t, group, dim, film_max, pairs, ab, cap, a.nx, a.ny, a.nz);
+        __syncthreads();
+        const int found = min(t.head[1], cap);
+        const int w = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6);
+        for (int p = w; p < found; p += nw) {
+            const MergeResult r = merge_pair_wave<Q, S>(pairs[p], labels, f, film_max, a);
+            if ((threadIdx.x & 63) == 0) res[p] = r;
+        }
+        __syncthreads();
+    }
+    stage_out_body(o);
+}
+
+hipError_t launch_pass_tail(int q, int storage, const BubbleTab& t, const int32_t* group,
+                            int film_max, MergePair* pairs, int32_t* ab, MergeResult* res,
+                            int cap, int do_pairs, const StageOut& o, const void* f,
+                            const uint32_t* labels, const FieldArgs& a, hipStream_t st)
+{
+    const int dim = q == 9 ? 2 : 3;
+    SC_DISPATCH(q, storage,
+                hipLaunchKernelGGL((k_pass_tail<QQ, SS>), dim3(1), dim3(1024), 0, st, t, group,
+                                   dim, film_max, pairs, ab, res, cap, do_pairs, o,
+                                   (const SS*)f, labels, a));
     return hipGetLastError();
 }
 

@@ -97,7 +97,7 @@ class BatchResult(C.Structure):
 # Entry points declared in include/sc.h (checked by the CPU test suite).
 EXPORTS = (
     "sc_abi_version", "sc_last_error", "sc_params_init", "sc_create", "sc_destroy",
-    "sc_seed_nuclei", "sc_step", "sc_fields", "sc_fields_device", "sc_laplacian_p",
+    "sc_seed_nuclei", "sc_step", "sc_step_graphs", "sc_fields", "sc_fields_device", "sc_laplacian_p",
     "sc_laplacian_p_device", "sc_label_bubbles", "sc_label_bubbles_noalloc",
     "sc_merge_events", "sc_topo_events", "sc_bubbles", "sc_last_labels", "sc_nuclei",
     "sc_source_ledger", "sc_owner", "sc_buoyancy_density", "sc_film_geometry", "sc_gas_density",
@@ -145,6 +145,7 @@ def load_library(path=LIB_PATH):
         "sc_bubbles": (C.c_int, [P, P, C.c_int32, P]),
         "sc_last_labels": (C.c_int, [P, P]),
         "sc_nuclei": (C.c_int, [P, P, P]),
+        "sc_step_graphs": (C.c_int, [P, C.c_int32]),
         "sc_label_bubbles_noalloc": (C.c_int, [P, P, P, P]),
         "sc_source_ledger": (C.c_int, [P, P, P]),
         "sc_get_gas_populations": (C.c_int, [P, P]),
@@ -343,6 +344,10 @@ class Sim:
 
     def step(self, n):
         _check(self._lib.sc_step(self._h, int(n)))
+
+    def step_graphs(self, enable):
+        """K-step blocks of a small box as HIP graphs (default on) or launched step by step."""
+        _check(self._lib.sc_step_graphs(self._h, 1 if enable else 0))
 
     def test_pass(self):
         _check(self._lib.sc_test_pass(self._h))

@@ -118,6 +118,7 @@ struct sc_sim {
     // host memory (stage, stage_n nuclei; the merge groups are staged there too) with one
     // synchronization
     DevBuf btab, pair_ab;
+    int btab_n = 0;  // nucleus count the table in btab is laid out for (its last pass)
     int pair_cap = 0;
     bool group_dirty = true;
     char* stage = nullptr;      // host address
@@ -327,7 +328,7 @@ std::vector<StepShape> tune_candidates(int q)
     std::vector<StepShape> c;
     if (q == SC_D2Q9) {
         for (int tx : {64, 128, 256, 512})
-            for (int tz : {2, 4, 8, 16, 32, 64})
+            for (int tz : {1, 2, 4, 8, 16, 32, 64})
                 for (int v : {1, 3}) c.push_back(StepShape{tx, 1, tz, v});
     } else {
         const int tiles[][2] = {{32, 8}, {64, 4}, {64, 8}, {128, 4}, {128, 8}, {256, 4}};
@@ -533,9 +534,8 @@ int label_current(sc_sim* s, uint32_t* labels_d, uint32_t* ncomp_host, const uin
         HIPX(launch_mask_from_rho(s->q, s->p.storage, s->f[s->cur], (uint32_t*)s->parent.p, fa,
                                   s->stream));
     }
-    HIPX(launch_union(s->q, (uint32_t*)s->parent.p, fa, s->stream));
     uint32_t* ncomp_d = (uint32_t*)((char*)s->small.p + 64);
-    HIPX(launch_fill_i32((int32_t*)ncomp_d, 0, 1, s->stream));
+    HIPX(launch_union(s->q, (uint32_t*)s->parent.p, ncomp_d, fa, s->stream));
     HIPX(launch_flatten((uint32_t*)s->parent.p, labels_d, ncomp_d, s->N, s->stream));
     if (ncomp_host)
         HIPX(hipMemcpyAsync(ncomp_host, ncomp_d, sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -748,7 +748,20 @@ int pass_prepare(sc_sim* s, bool with_criterion)
             HIPX(launch_fill_i32((int32_t*)s->slots.p, -1, s->N, s->stream));
             s->slots_ready = true;
         }
-        TRY(ensure(s, s->btab, bubble_tab_bytes(n)));
+        if (!s->btab.p || s->btab.bytes < bubble_tab_bytes(n)) {
+            // a new table buffer: the old table's bubbles leave the slot map now, and the new
+            // head starts at zero bubbles
+            if (s->btab.p) {
+                const BubbleTab old = bubble_tab_view(s->btab.p, s->btab_n);
+                HIPX(launch_bubble_table((const uint32_t*)s->labels.p, (const int64_t*)s->nodes.p,
+                                         0, old, old, (int32_t*)s->slots.p, field_args(s),
+                                         s->stream));
+                HIPX(hipStreamSynchronize(s->stream));
+            }
+            TRY(ensure(s, s->btab, bubble_tab_bytes(n)));
+            HIPX(launch_fill_i32((int32_t*)s->btab.p, 0, 16, s->stream));
+            s->btab_n = n;
+        }
         if (with_criterion && n >= 2) {
             const Stage st = stage_view(s->stage, n);
             if (s->group_dirty) {
@@ -791,8 +804,9 @@ int pass_enqueue(sc_sim* s, bool with_criterion)
     int pair_cap = 0;
     if (n > 0) {
         t = bubble_tab_view(s->btab.p, n);
-        HIPX(launch_bubble_table((const uint32_t*)s->labels.p, (const int64_t*)s->nodes.p, n, t,
-                                 (int32_t*)s->slots.p, fa, s->stream));
+        const BubbleTab prev = bubble_tab_view(s->btab.p, s->btab_n);
+        HIPX(launch_bubble_table((const uint32_t*)s->labels.p, (const int64_t*)s->nodes.p, n,
+                                 prev, t, (int32_t*)s->slots.p, fa, s->stream));
         HIPX(launch_stats((const uint32_t*)s->labels.p, (const int32_t*)s->slots.p, t.anchors,
                           t.count, t.sums, fa, s->stream));
         if (with_criterion && n >= 2) {
@@ -1035,8 +1049,8 @@ int pass_finish(sc_sim* s, bool with_criterion)
     }
 
     if (s->p.barrier) TRY(build_owner(s, nb));
-    if (nb > 0)  // slot map back to "no bubble" for the next pass
-        HIPX(launch_set_slots((int32_t*)s->slots.p, t.distinct, nb, 1, s->stream));
+    // (the slot map keeps this pass's bubbles until the next pass's bubble table clears them)
+    if (n > 0) s->btab_n = n;
 
     build_schedule(s, schedule_chunk_len(s));
     if (s->rate > 0.0) TRY(upload_schedule(s));
@@ -1436,7 +1450,7 @@ static int run_pass_graph(sc_sim* s)
     const int c0 = s->cur;
     const FieldArgs fa = field_args(s);
     const int n = (int)s->rad.size();
-    const int meta[6] = {n, s->pair_cap, s->two ? 1 : 0, c0, s->p.film_max, s->d};
+    const int meta[7] = {n, s->pair_cap, s->two ? 1 : 0, c0, s->p.film_max, s->d, s->btab_n};
     const void* ptrs[16] = {s->labels.p, s->parent.p, s->small.p, s->partials.p, s->slots.p,
                             s->btab.p, (void*)s->stage_dev, s->pair_buf.p, s->res_buf.p, s->pair_ab.p,
                             s->nodes.p, (void*)s->stage, s->f[c0], s->fv[c0],
@@ -1748,14 +1762,13 @@ int sc_label_bubbles_noalloc(sc_sim* s, const uint8_t* mask_dev, uint32_t* label
     uint32_t* parent = base;
     uint32_t* ncomp_d = base + kScratchMaxNodes;  // 256-byte aligned: kScratchMaxNodes * 4
     const FieldArgs fa = field_args(s);
-    // every parent entry below N is written by the mask kernel; the counter is cleared by a
-    // kernel (the array keeps the previous call's contents)
+    // every parent entry below N is written by the mask kernel; the counter is cleared by the
+    // union kernel (the array keeps the previous call's contents)
     if (mask_dev)
         HIPX(launch_mask_from_bytes(mask_dev, parent, s->N, s->stream));
     else
         HIPX(launch_mask_from_rho(s->q, s->p.storage, s->f[s->cur], parent, fa, s->stream));
-    HIPX(launch_union(s->q, parent, fa, s->stream));
-    HIPX(launch_fill_i32((int32_t*)ncomp_d, 0, 1, s->stream));
+    HIPX(launch_union(s->q, parent, ncomp_d, fa, s->stream));
     HIPX(launch_flatten(parent, labels_dev, ncomp_d, s->N, s->stream));
     uint32_t nc = 0;
     HIPX(hipMemcpyAsync(&nc, ncomp_d, sizeof(nc), hipMemcpyDeviceToHost, s->stream));

@@ -127,7 +127,10 @@ hipError_t launch_mask_from_rho(int q, int storage, const void* f, uint32_t* par
                                 const FieldArgs& a, hipStream_t st);
 hipError_t launch_mask_from_bytes(const uint8_t* mask_d, uint32_t* parent, int64_t N,
                                   hipStream_t st);
-hipError_t launch_union(int q, uint32_t* parent, const FieldArgs& a, hipStream_t st);
+// Union-find of the mask in parent (tile-local in LDS, then the links between tiles); with
+// zero_counter, the counter of the flatten that follows is set to zero.
+hipError_t launch_union(int q, uint32_t* parent, uint32_t* zero_counter, const FieldArgs& a,
+                        hipStream_t st);
 hipError_t launch_flatten(uint32_t* parent, uint32_t* labels, uint32_t* ncomp_d, int64_t N,
                           hipStream_t st);
 
@@ -181,9 +184,11 @@ struct BubbleTab {
 };
 size_t bubble_tab_bytes(int n);
 BubbleTab bubble_tab_view(void* base, int n);
+// prev: the table of the previous pass (same buffer, its own nucleus count): its bubbles' slots
+// are cleared first.
 hipError_t launch_bubble_table(const uint32_t* labels, const int64_t* nuc_node, int n,
-                               const BubbleTab& t, int32_t* slot_of_root, const FieldArgs& a,
-                               hipStream_t st);
+                               const BubbleTab& prev, const BubbleTab& t, int32_t* slot_of_root,
+                               const FieldArgs& a, hipStream_t st);
 // Candidate pairs of the merge test: FP64 centroids and radii formed as the host forms them,
 // then every pair a < b of different merge groups (group[k]: representative of nucleus k) within
 // radius_a + radius_b + film_max + 1e-6 (a superset of the host's exact test), compacted into

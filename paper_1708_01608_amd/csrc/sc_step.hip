@@ -58,40 +58,43 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
     float cur[9], nxt[9];
     A dcur = (A)0, dnxt = (A)0;
 
-    // prologue: row y0 - 1 (psi only) and row y0 (psi, populations kept)
+    // prologue: rows y0 - 1 (psi only), y0 and y0 + 1 (psi, populations kept); the three rows'
+    // loads are issued together, so the block waits out one memory latency for them
     {
-        const int y = wrap_once(y0 - 1, ny);
-        const int ym = wrap_once(y - 1, ny), yp = wrap_once(y + 1, ny);
+        const int ya = wrap_once(y0 - 1, ny), yb = y0, yc = wrap_once(y0 + 1, ny);
+        float g[9], h[3][9];
         if (own) {
-            float g[9];
-            pull_node<9>(src, N, nx, ny, x, xm, xp, y, ym, yp, 0, 0, 0, g);
-            ps[0][tx + 1] = psi_f(c.rho_ref + sum_dev<9, A>(g));
+            pull_node<9>(src, N, nx, ny, x, xm, xp, ya, wrap_once(ya - 1, ny), wrap_once(ya + 1, ny),
+                         0, 0, 0, g);
+            pull_node<9>(src, N, nx, ny, x, xm, xp, yb, wrap_once(yb - 1, ny), wrap_once(yb + 1, ny),
+                         0, 0, 0, cur);
+            pull_node<9>(src, N, nx, ny, x, xm, xp, yc, wrap_once(yc - 1, ny), wrap_once(yc + 1, ny),
+                         0, 0, 0, nxt);
         }
         if (ring) {
-            float h[9];
-            pull_node<9>(src, N, nx, ny, hx, hxm, hxp, y, ym, yp, 0, 0, 0, h);
-            ps[0][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
+            const int yy[3] = {ya, yb, yc};
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                pull_node<9>(src, N, nx, ny, hx, hxm, hxp, yy[r], wrap_once(yy[r] - 1, ny),
+                             wrap_once(yy[r] + 1, ny), 0, 0, 0, h[r]);
         }
-    }
-    {
-        const int y = y0;
-        const int ym = wrap_once(y - 1, ny), yp = wrap_once(y + 1, ny);
         if (own) {
-            pull_node<9>(src, N, nx, ny, x, xm, xp, y, ym, yp, 0, 0, 0, cur);
+            ps[0][tx + 1] = psi_f(c.rho_ref + sum_dev<9, A>(g));
             dcur = sum_dev<9, A>(cur);
             ps[1][tx + 1] = psi_f(c.rho_ref + dcur);
+            dnxt = sum_dev<9, A>(nxt);
+            ps[2][tx + 1] = psi_f(c.rho_ref + dnxt);
         }
         if (ring) {
-            float h[9];
-            pull_node<9>(src, N, nx, ny, hx, hxm, hxp, y, ym, yp, 0, 0, 0, h);
-            ps[1][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h));
+#pragma unroll
+            for (int r = 0; r < 3; ++r) ps[r][hl] = psi_f(c.rho_ref + sum_dev<9, A>(h[r]));
         }
     }
 
     for (int y = y0; y < ye; ++y) {
         const int s = (y - y0 + 1) & 3;
         const int sn = (s + 1) & 3, sp = (s + 3) & 3;
-        {
+        if (y > y0) {  // row y0 + 1 came with the prologue
             const int yn = wrap_once(y + 1, ny);
             const int ym = wrap_once(yn - 1, ny), yp = wrap_once(yn + 1, ny);
             if (own) {

@@ -402,7 +402,7 @@ template <int Q>
 struct UnionTile;
 template <>
 struct UnionTile<9> {
-    static constexpr int TX = 64, TY = 64, TZ = 1;
+    static constexpr int TX = 32, TY = 32, TZ = 1;
 };
 template <>
 struct UnionTile<19> {
@@ -451,8 +451,11 @@ __device__ __forceinline__ bool local_link(int lx, int ly, int lz, int x, int y,
 }
 
 template <int Q>
-__global__ void __launch_bounds__(1024) k_union_local(uint32_t* parent, FieldArgs a)
+__global__ void __launch_bounds__(1024) k_union_local(uint32_t* parent, uint32_t* zero_counter,
+                                                      FieldArgs a)
 {
+    // the component counter of the flatten that follows starts at zero
+    if (zero_counter && blockIdx.x == 0 && threadIdx.x == 0) *zero_counter = 0u;
     using L = lat<Q>;
     using T = UnionTile<Q>;
     constexpr int NT = T::TX * T::TY * T::TZ;
@@ -1168,21 +1171,24 @@ hipError_t launch_mask_from_bytes(const uint8_t* mask_d, uint32_t* parent, int64
 }
 
 template <int Q>
-static hipError_t launch_union_tiled(uint32_t* parent, const FieldArgs& a, hipStream_t st)
+static hipError_t launch_union_tiled(uint32_t* parent, uint32_t* zero_counter, const FieldArgs& a,
+                                     hipStream_t st)
 {
     using T = UnionTile<Q>;
     const int64_t tiles = (int64_t)((a.nx + T::TX - 1) / T::TX) * ((a.ny + T::TY - 1) / T::TY) *
                           ((a.nz + T::TZ - 1) / T::TZ);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_union_local<Q>), dim3((unsigned)tiles), dim3(1024), 0, st, parent, a);
+    hipLaunchKernelGGL((k_union_local<Q>), dim3((unsigned)tiles), dim3(1024), 0, st, parent,
+                       zero_counter, a);
     hipLaunchKernelGGL((k_union_cross<Q>), grid_for(a.N), dim3(256), 0, st, parent, a);
     return hipGetLastError();
 }
 
-hipError_t launch_union(int q, uint32_t* parent, const FieldArgs& a, hipStream_t st)
+hipError_t launch_union(int q, uint32_t* parent, uint32_t* zero_counter, const FieldArgs& a,
+                        hipStream_t st)
 {
-    if (q == 9) return launch_union_tiled<9>(parent, a, st);
-    if (q == 19) return launch_union_tiled<19>(parent, a, st);
+    if (q == 9) return launch_union_tiled<9>(parent, zero_counter, a, st);
+    if (q == 19) return launch_union_tiled<19>(parent, zero_counter, a, st);
     return hipErrorInvalidValue;
 }
 
@@ -1313,10 +1319,16 @@ BubbleTab bubble_tab_view(void* base, int n)
 // comparisons, a few microseconds for hundreds of nuclei).
 __global__ void __launch_bounds__(1024) k_bubble_table(const uint32_t* labels,
                                                        const int64_t* nuc_node, int n, int64_t N,
-                                                       BubbleTab t, int32_t* slot_of_root, int nx,
-                                                       int ny)
+                                                       BubbleTab prev, BubbleTab t,
+                                                       int32_t* slot_of_root, int nx, int ny)
 {
     __shared__ int nb;
+    // the previous pass's bubbles leave the slot map first (prev: the same buffer laid out for
+    // the nucleus count of that pass; its head is zero before the first pass)
+    const int nb_prev = prev.head[0];
+    for (int b = threadIdx.x; b < nb_prev; b += blockDim.x)
+        slot_of_root[prev.distinct[b] - 1] = -1;
+    __syncthreads();
     if (threadIdx.x == 0) nb = 0;
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
         const int64_t nd = nuc_node[k];
@@ -1357,12 +1369,11 @@ __global__ void __launch_bounds__(1024) k_bubble_table(const uint32_t* labels,
 }
 
 hipError_t launch_bubble_table(const uint32_t* labels, const int64_t* nuc_node, int n,
-                               const BubbleTab& t, int32_t* slot_of_root, const FieldArgs& a,
-                               hipStream_t st)
+                               const BubbleTab& prev, const BubbleTab& t, int32_t* slot_of_root,
+                               const FieldArgs& a, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bubble_table, dim3(1), dim3(1024), 0, st, labels, nuc_node, n, a.N, t,
-                       slot_of_root, a.nx, a.ny);
+    hipLaunchKernelGGL(k_bubble_table, dim3(1), dim3(1024), 0, st, labels, nuc_node, n, a.N,
+                       prev, t, slot_of_root, a.nx, a.ny);
     return hipGetLastError();
 }
 

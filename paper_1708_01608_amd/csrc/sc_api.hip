@@ -333,7 +333,7 @@ std::vector<StepShape> tune_candidates(int q)
     } else {
         const int tiles[][2] = {{32, 8}, {64, 4}, {64, 8}, {128, 4}, {128, 8}, {256, 4}};
         for (auto& t : tiles)
-            for (int tz : {16, 32, 64, 128})
+            for (int tz : {16, 32, 64, 128, 256, 512})
                 for (int v : {1, 2, 3}) c.push_back(StepShape{t[0], t[1], tz, v});
     }
     return c;

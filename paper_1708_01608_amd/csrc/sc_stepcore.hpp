@@ -178,6 +178,12 @@ __device__ __forceinline__ A e_dot(int i, A ux, A uy, A uz)
 // difference: f_i - f_i^eq = g_i - (w_i drho + w_i rho P_i)).  In FP32 the w_i drho term takes
 // the weight as a pair of floats.  Population i goes to byte offset
 // lane sizeof(S) from the direction's base dst + i N (below 2^32, as for the loads).
+//
+// With 16-bit storage the stored value's rounding (2^-11 or 2^-8 relative) dwarfs the FP32
+// arithmetic's, so the collision there takes the short form
+//   g_i* = g_i + omega (w_i (drho + rho P_i) - g_i)
+// with P of an opposite pair sharing its even part (P_i = S + 3 e.u, P_ibar = S - 3 e.u,
+// S = 4.5 (e.u)^2 - 1.5 u^2): three FMAs a direction instead of five.
 template <int Q, typename A, typename S, bool NT = false>
 __device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint32_t lane,
                                             const float* g, A drho, A rho, A ux, A uy, A uz,
@@ -186,6 +192,25 @@ __device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint
     constexpr bool three = Q == 19;
     const A usq15 = (A)1.5 * (three ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy);
     const uint32_t boff = lane * (uint32_t)sizeof(S);
+    if constexpr (sizeof(S) == 2) {
+        // rest population, then the opposite pairs (i odd, i + 1 its reverse)
+        auto put_one = [&](int i, A P) {
+            const A gi = (A)g[i];
+            const A feq = weight<Q, A>(i) * fmad(rho, P, drho);
+            const A gs = fmad(omega, feq - gi, gi);
+            char* base = reinterpret_cast<char*>(dst + (int64_t)i * N);
+            put<NT, S>(reinterpret_cast<S*>(base + boff), store_f<S>((float)gs));
+        };
+        put_one(0, -usq15);
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const A eu = e_dot<Q, A>(i, ux, uy, uz);
+            const A even = fmad((A)4.5 * eu, eu, -usq15);
+            put_one(i, fmad((A)3, eu, even));
+            put_one(i + 1, fmad((A)-3, eu, even));
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const A eu = e_dot<Q, A>(i, ux, uy, uz);

@@ -402,11 +402,11 @@ template <int Q>
 struct UnionTile;
 template <>
 struct UnionTile<9> {
-    static constexpr int TX = 32, TY = 32, TZ = 1;
+    static constexpr int TX = 32, TY = 32, TZ = 1, THREADS = 1024;  // one node per thread
 };
 template <>
 struct UnionTile<19> {
-    static constexpr int TX = 16, TY = 16, TZ = 16;
+    static constexpr int TX = 16, TY = 16, TZ = 16, THREADS = 256;  // sixteen nodes per thread
 };
 
 __device__ __forceinline__ uint32_t lds_load(const uint32_t* p)
@@ -451,8 +451,9 @@ __device__ __forceinline__ bool local_link(int lx, int ly, int lz, int x, int y,
 }
 
 template <int Q>
-__global__ void __launch_bounds__(1024) k_union_local(uint32_t* parent, uint32_t* zero_counter,
-                                                      FieldArgs a)
+__global__ void __launch_bounds__(UnionTile<Q>::THREADS) k_union_local(uint32_t* parent,
+                                                                       uint32_t* zero_counter,
+                                                                       FieldArgs a)
 {
     // the component counter of the flatten that follows starts at zero
     if (zero_counter && blockIdx.x == 0 && threadIdx.x == 0) *zero_counter = 0u;
@@ -1178,8 +1179,8 @@ static hipError_t launch_union_tiled(uint32_t* parent, uint32_t* zero_counter, c
     const int64_t tiles = (int64_t)((a.nx + T::TX - 1) / T::TX) * ((a.ny + T::TY - 1) / T::TY) *
                           ((a.nz + T::TZ - 1) / T::TZ);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_union_local<Q>), dim3((unsigned)tiles), dim3(1024), 0, st, parent,
-                       zero_counter, a);
+    hipLaunchKernelGGL((k_union_local<Q>), dim3((unsigned)tiles), dim3(T::THREADS), 0, st,
+                       parent, zero_counter, a);
     hipLaunchKernelGGL((k_union_cross<Q>), grid_for(a.N), dim3(256), 0, st, parent, a);
     return hipGetLastError();
 }

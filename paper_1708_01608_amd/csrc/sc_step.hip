@@ -128,6 +128,21 @@ __global__ void __launch_bounds__(TX) k_step2d(const S* __restrict__ src, S* __r
     }
 }
 
+// Ring cell (hlx, hly) of thread t in the psi tile of a wx x wy tile: the rows below and above
+// (wx + 2 cells each, corners included), then the left and right columns (wy cells each).
+__device__ __forceinline__ void ring_cell(int t, int wx, int wy, int& hlx, int& hly)
+{
+    if (t < wx + 2) {
+        hlx = t; hly = 0;
+    } else if (t < 2 * (wx + 2)) {
+        hlx = t - (wx + 2); hly = wy + 1;
+    } else if (t < 2 * (wx + 2) + wy) {
+        hlx = 0; hly = 1 + t - 2 * (wx + 2);
+    } else {
+        hlx = wx + 1; hly = 1 + t - 2 * (wx + 2) - wy;
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // D3Q19: a block owns a TX x TY tile of an x-y plane and marches `planes` planes in z.
 // ------------------------------------------------------------------------------------------
@@ -207,33 +222,84 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
     for (int z = z0; z < ze; ++z) {
         const int s = (z - z0 + 1) & 3;
         const int sn = (s + 1) & 3, sp = (s + 3) & 3;
-        {
-            const int zn = wrap_once(z + 1, nz);
-            const int zm = wrap_once(zn - 1, nz), zp = wrap_once(zn + 1, nz);
-            if (own) {
-                pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, zn, zm, zp, nxt);
+        if constexpr (std::is_same<A, double>::value) {
+            // FP64 arithmetic fills the 128 VGPRs of a 1024-thread block, so the loop is shaped
+            // for registers: every lane loads plane z+1 (a lane outside a ragged tile its clamped
+            // in-box node, harmlessly) and the ring's loads and sum form one block, so both sets
+            // of loads are in flight together and none is left pending past the sums (a pending
+            // load would make the copy into cur wait for every store of the plane); coordinates
+            // are derived from the thread index where they are used rather than held across
+            // the loop (held, they spill, and each reload waits for all loads in flight)
+            {
+                const int zn = wrap_once(z + 1, nz);
+                const int zm = wrap_once(zn - 1, nz), zp = wrap_once(zn + 1, nz);
+                const int tt = opaque(t);
+                const int ltx = tt % TX, lty = tt / TX;
+                {
+                    const int ox = x0 + min(ltx, wx - 1), oy = y0 + min(lty, wy - 1);
+                    pull_node<19>(src, N, nx, ny, ox, wrap_once(ox - 1, nx),
+                                  wrap_once(ox + 1, nx), oy, wrap_once(oy - 1, ny),
+                                  wrap_once(oy + 1, ny), zn, zm, zp, nxt);
+                }
+                if (ring) {
+                    int rlx, rly;
+                    ring_cell(tt, wx, wy, rlx, rly);
+                    const int ox = wrap_once(x0 - 1 + rlx, nx), oy = wrap_once(y0 - 1 + rly, ny);
+                    float h[19];
+                    pull_node<19>(src, N, nx, ny, ox, wrap_once(ox - 1, nx),
+                                  wrap_once(ox + 1, nx), oy, wrap_once(oy - 1, ny),
+                                  wrap_once(oy + 1, ny), zn, zm, zp, h);
+                    ps[sn][rly][rlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
+                }
                 dnxt = sum_dev<19, A>(nxt);
-                ps[sn][ty + 1][tx + 1] = psi_f(c.rho_ref + dnxt);
+                if (own) ps[sn][lty + 1][ltx + 1] = psi_f(c.rho_ref + dnxt);
             }
-            if (ring) {
-                float h[19];
-                pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, zn, zm, zp, h);
-                ps[sn][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
+            __syncthreads();
+            if (own) {
+                const int tt = opaque(t);
+                const int ltx = tt % TX, lty = tt / TX;
+                const A pc = ps[s][lty + 1][ltx + 1];
+                A fx, fy, fz;
+                interaction_sum<19, A>(
+                    [&](int i) {
+                        const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
+                        return ps[slot][lty + 1 + L::ey[i]][ltx + 1 + L::ex[i]];
+                    },
+                    fx, fy, fz);
+                const A gp = -c.G * pc;
+                const int ox = x0 + ltx, oy = y0 + lty;
+                collide_store<19, A, S, NT, EXT, true>(dst, N, (uint32_t)(ox + nx * (oy + ny * z)),
+                                                      cur, dcur, gp * fx, gp * fy, gp * fz, c);
             }
-        }
-        __syncthreads();
-        if (own) {
-            const A pc = ps[s][ty + 1][tx + 1];
-            A fx, fy, fz;
-            interaction_sum<19, A>(
-                [&](int i) {
-                    const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
-                    return ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
-                },
-                fx, fy, fz);
-            const A gp = -c.G * pc;
-            collide_store<19, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
-                                        gp * fx, gp * fy, gp * fz, c);
+        } else {
+            {
+                const int zn = wrap_once(z + 1, nz);
+                const int zm = wrap_once(zn - 1, nz), zp = wrap_once(zn + 1, nz);
+                if (own) {
+                    pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, zn, zm, zp, nxt);
+                    dnxt = sum_dev<19, A>(nxt);
+                    ps[sn][ty + 1][tx + 1] = psi_f(c.rho_ref + dnxt);
+                }
+                if (ring) {
+                    float h[19];
+                    pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, zn, zm, zp, h);
+                    ps[sn][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
+                }
+            }
+            __syncthreads();
+            if (own) {
+                const A pc = ps[s][ty + 1][tx + 1];
+                A fx, fy, fz;
+                interaction_sum<19, A>(
+                    [&](int i) {
+                        const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
+                        return ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
+                    },
+                    fx, fy, fz);
+                const A gp = -c.G * pc;
+                collide_store<19, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur,
+                                                dcur, gp * fx, gp * fy, gp * fz, c);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 19; ++i) cur[i] = nxt[i];

@@ -10,6 +10,20 @@
 
 namespace sc {
 
+// The value itself, opaque to the optimizer: what is derived from it is computed where it is used
+// instead of being hoisted out of a loop, or shared with an earlier use, and kept live (with 128
+// VGPRs, spilled) across the collision.
+__device__ __forceinline__ int opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ float opaque(float v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 struct StepGrid {
     int gx, gy, gz;  // tiles along x, y and plane chunks
     int remap;       // 1: contiguous tile ranges per XCD (8 XCDs, round-robin dispatch)
@@ -184,7 +198,7 @@ __device__ __forceinline__ A e_dot(int i, A ux, A uy, A uz)
 //   g_i* = g_i + omega (w_i (drho + rho P_i) - g_i)
 // with P of an opposite pair sharing its even part (P_i = S + 3 e.u, P_ibar = S - 3 e.u,
 // S = 4.5 (e.u)^2 - 1.5 u^2): three FMAs a direction instead of five.
-template <int Q, typename A, typename S, bool NT = false>
+template <int Q, typename A, typename S, bool NT = false, bool RECVT = false>
 __device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint32_t lane,
                                             const float* g, A drho, A rho, A ux, A uy, A uz,
                                             A omega)
@@ -216,7 +230,9 @@ __device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint
         const A eu = e_dot<Q, A>(i, ux, uy, uz);
         const A P = fmad(eu, fmad((A)4.5, eu, (A)3), -usq15);
         const A w = weight<Q, A>(i);
-        const A gi = (A)g[i];
+        // RECVT: converted again here rather than kept from the momentum sums (with FP64, 19
+        // doubles live through the velocity spill in a 1024-thread block)
+        const A gi = RECVT ? (A)opaque(g[i]) : (A)g[i];
         A h = fmad(-w, drho, gi);
         if constexpr (std::is_same<A, float>::value) h = fmad(-weight_lo<Q>(i), drho, h);
         const A d = fmad(w * rho, P, -h);
@@ -228,7 +244,7 @@ __device__ __forceinline__ void relax_store(S* __restrict__ dst, int64_t N, uint
 
 // Forced collision of one component: velocity-shift forcing u_eq = (j + tau F) / rho, then the
 // BGK relaxation and the store.
-template <int Q, typename A, typename S, bool NT = false, bool EXT = false>
+template <int Q, typename A, typename S, bool NT = false, bool EXT = false, bool RECVT = false>
 __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, uint32_t lane,
                                               const float* g, A drho, A Fx, A Fy, A Fz,
                                               const Coef<A>& c)
@@ -256,7 +272,7 @@ __device__ __forceinline__ void collide_store(S* __restrict__ dst, int64_t N, ui
     const A ux = fmad(c.tau, Fx, jx) * inv;
     const A uy = fmad(c.tau, Fy, jy) * inv;
     const A uz = three ? fmad(c.tau, Fz, jz) * inv : (A)0;
-    relax_store<Q, A, S, NT>(dst, N, lane, g, drho, rho, ux, uy, uz, c.omega);
+    relax_store<Q, A, S, NT, RECVT>(dst, N, lane, g, drho, rho, ux, uy, uz, c.omega);
 }
 
 }  // namespace sc

@@ -371,6 +371,25 @@ def test_invalid_seed_arguments():
     g.step(3)  # the handle is still usable
 
 
+@pytest.mark.parametrize("storage,compute", [("f32", "f32"), ("f16", "f32"), ("bf16", "f32")])
+def test_3d_variants_bitwise_equal_fp32_arithmetic(storage, compute):
+    # FP32 arithmetic on every storage: plain, pipelined and non-temporal variants give the same
+    # bits on a ragged box
+    spec = W.SimSpec(name="tiles32", q=19, nx=70, ny=40, nz=30, tau=0.9, K=10,
+                     centres=np.array([(20.0, 11.0, 7.0), (51.0, 30.0, 22.0)]),
+                     radii=np.full(2, 7.0), budgets=np.full(2, 1e-2), rate=1e-4)
+    shapes = [(32, 4, 5, 1), (64, 8, 16, 2), (256, 4, 11, 3), (128, 8, 30, 1)]
+    ref = None
+    for tx, ty, tz, v in shapes:
+        g = gpu_from_spec(spec, tile=(tx, ty, tz), variant=v, storage=storage, compute=compute)
+        g.step(30)
+        f = g.get_populations()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), (tx, ty, tz, v)
+        g.close()
+
+
 # ---- tiling is invisible: every tile and variant gives the same bits; tuning keeps the state ------
 @pytest.mark.parametrize("q,shape", [(9, (150, 90, 1)), (19, (70, 40, 30))])
 def test_tiles_variants_bitwise_equal_and_autotune_keeps_state(q, shape):
@@ -382,7 +401,7 @@ def test_tiles_variants_bitwise_equal_and_autotune_keeps_state(q, shape):
                      radii=np.full(3, 7.0), budgets=np.full(3, 1e-2), rate=1e-4)
     shapes = ([(64, 1, 3, 1), (128, 1, 8, 1), (256, 1, 64, 1)] if q == 9 else
               [(32, 4, 5, 1), (64, 8, 16, 1), (32, 8, 7, 2), (16, 16, 64, 2), (64, 4, 9, 3),
-               (128, 8, 6, 3)])
+               (128, 8, 6, 3), (256, 4, 11, 3)])
     ref = None
     for tx, ty, tz, v in shapes:
         g = gpu_from_spec(spec, tile=(tx, ty, tz), variant=v)

@@ -443,6 +443,15 @@ def main():
     out["roofline"]["measured_copy_GBps"] = round(copy_gbs, 1)
     out["roofline"]["measured_read_GBps"] = round(read_gbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
+    if spec.q == 19 and spec.two_component is None:
+        # the step's own memory pattern with its arithmetic left out: flat (one node per
+        # thread) and marching the step kernel's tiles
+        tx, ty, tz = r["tile"][:3]
+        flat_gbs, march_gbs = sc.pattern_probe(spec.nx, spec.ny, spec.nz, args.storage,
+                                               (tx, ty, tz), 5)
+        out["roofline"]["measured_pattern_flat_GBps"] = round(flat_gbs, 1)
+        out["roofline"]["measured_pattern_march_GBps"] = round(march_gbs, 1)
+        out["roofline"]["frac_of_pattern_march"] = round(achieved / march_gbs, 4)
     patterns = (args.workload == "foam_3d" and not args.no_patterns and not args.barrier and
                 not args.gravity and args.tile is None and args.storage == "f32")
     err_spec = err_fields = None

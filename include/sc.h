@@ -376,6 +376,20 @@ int sc_batch_destroy(struct sc_batch* b);
  * ceiling that the step kernel's bandwidth is compared with.  Uses the null stream. */
 int sc_hbm_probe(size_t bytes, int32_t reps, double* copy_GBps, double* read_GBps);
 
+/* The D3Q19 step's memory pattern without its arithmetic (pull streaming, Fig. 1 step 1): for
+ * an nx x ny x nz box of `storage` (SC_STORE_F32 / F16 / BF16) elements, 19 arrays of
+ * populations, every population of every node read from its upstream neighbour (periodic) and
+ * written with non-temporal stores, on freshly allocated device memory (2 x 19 N elements,
+ * freed on return; the null stream).  flat_GBps: one node per thread; march_GBps: blocks of
+ * tile_x * tile_y (<= 1024) threads, each a tile_x x tile_y tile marching tile_z planes in
+ * the step kernel's block order.  Best of `reps` timed launches after one untimed, as read +
+ * written bytes per second.  SC_E_INVAL for a bad box (ny, nz <= 65535; N elements of at
+ * most 2^32 bytes per direction), tile, storage or reps; SC_E_DEVICE or the allocation's
+ * error otherwise. */
+int sc_pattern_probe(int32_t nx, int32_t ny, int32_t nz, int32_t storage, int32_t tile_x,
+                     int32_t tile_y, int32_t tile_z, int32_t reps, double* flat_GBps,
+                     double* march_GBps);
+
 typedef struct sc_sim sc_sim;
 typedef struct sc_batch sc_batch;
 

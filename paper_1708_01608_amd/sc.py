@@ -106,7 +106,7 @@ EXPORTS = (
     "sc_get_gas_populations", "sc_set_gas_populations",
     "sc_test_pass", "sc_profile", "sc_profile_read", "sc_step_config", "sc_compute_type",
     "sc_batch_create", "sc_batch_run", "sc_batch_fields", "sc_batch_destroy", "sc_autotune",
-    "sc_hbm_probe", "sc_batch_tune",
+    "sc_hbm_probe", "sc_pattern_probe", "sc_batch_tune",
 )
 
 _lib = None
@@ -172,6 +172,8 @@ def load_library(path=LIB_PATH):
         "sc_batch_destroy": (C.c_int, [P]),
         "sc_autotune": (C.c_int, [P, C.c_int32, P, C.c_int32, P]),
         "sc_hbm_probe": (C.c_int, [C.c_size_t, C.c_int32, P, P]),
+        "sc_pattern_probe": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_int32, C.c_int32, C.c_int32, P, P]),
         "sc_batch_tune": (C.c_int, [P, C.c_int32, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -190,6 +192,16 @@ def _check(rc):
     if rc != SC_OK:
         msg = load_library().sc_last_error()
         raise ScError(rc, msg.decode() if msg else "")
+
+
+def pattern_probe(nx, ny, nz, storage="f32", tile=(256, 4, 64), reps=5):
+    """(flat GB/s, marching GB/s) of the D3Q19 step's memory pattern without its arithmetic."""
+    lib = load_library()
+    st = {"f32": 0, "f16": 1, "bf16": 2}[storage] if isinstance(storage, str) else int(storage)
+    f, m = C.c_double(), C.c_double()
+    _check(lib.sc_pattern_probe(int(nx), int(ny), int(nz), st, int(tile[0]), int(tile[1]),
+                                int(tile[2]), int(reps), C.byref(f), C.byref(m)))
+    return f.value, m.value
 
 
 def hbm_probe(nbytes=2550136832, reps=5):

@@ -271,3 +271,15 @@ def test_binding_refuses_overlapping_outputs():
     for start in (0x10000, 0x10000 + 8, 0x10000 - 8 * 99, 0x10000 + 799):
         with pytest.raises(ValueError):
             sc._check_disjoint(a, _FakeTensor(start, 100, 8), "p and lap")
+
+
+@pytest.mark.parametrize("args", [
+    (0, 8, 8, 0, 8, 8, 4, 1), (8, 8, 8, 3, 8, 8, 4, 1), (8, 8, 8, 0, 64, 32, 4, 1),
+    (8, 8, 8, 0, 8, 8, 0, 1), (8, 8, 8, 0, 8, 8, 4, 0),
+])
+def test_pattern_probe_arguments_are_checked(lib, args):
+    # rejected before any device call: empty box, unknown storage, tile above 1024 threads or
+    # without planes, no timed repetition
+    f, m = C.c_double(-1.0), C.c_double(-1.0)
+    assert lib.sc_pattern_probe(*args, C.byref(f), C.byref(m)) == sc.SC_E_INVAL
+    assert f.value == -1.0 and m.value == -1.0

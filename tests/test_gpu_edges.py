@@ -124,3 +124,13 @@ def test_mixture_smallest_box_matches_oracle():
     print(f"rho_l {e_rho:.3e} |du| {du:.3e} max|u| {umax:.3e} rho_v {e_v:.3e}")
     assert e_rho <= RHO_TOL and _u_ok((du, umax), U_TOL) and e_v <= RHO_TOL
     assert np.array_equal(g.last_labels(), o.labels())
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_bandwidth_probes_report_rates(storage):
+    # the ceilings the bench line quotes: positive rates, the pattern probe on a ragged box
+    # (tiles overhang the box in x and y, planes in z)
+    copy_gbs, read_gbs = sc.hbm_probe(1 << 26, 2)
+    assert copy_gbs > 0 and read_gbs > 0
+    flat, march = sc.pattern_probe(70, 40, 30, storage, (32, 8, 7), 2)
+    assert np.isfinite(flat) and np.isfinite(march) and flat > 0 and march > 0

@@ -471,22 +471,43 @@ __global__ void __launch_bounds__(UnionTile<Q>::THREADS) k_union_local(uint32_t*
         x = x0 + lx; y = y0 + ly; z = z0 + lz;
         return x < a.nx && y < a.ny && z < a.nz;
     };
+    static_assert(64 % T::TX == 0, "a wave holds whole tile rows");
+    // runs along x: a wave holds 64 consecutive tile nodes, whole rows, so one ballot of the gas
+    // mask gives every gas node the first node of its run, which becomes its parent (x-links
+    // need no union at all)
+    constexpr uint64_t kRowStarts = T::TX == 32 ? 0x0000000100000001ull
+                                                : 0x0001000100010001ull;  // lanes with lx == 0
+    static_assert(T::TX == 32 || T::TX == 16, "row-start mask for 16- or 32-node rows");
     for (int li = threadIdx.x; li < NT; li += blockDim.x) {
         int lx, ly, lz, x, y, z;
         const bool in = node(li, lx, ly, lz, x, y, z);
-        lp[li] = (in && parent[idx3(x, y, z, a.nx, a.ny)] != kLiquid) ? (uint32_t)li : kLiquid;
+        const bool gas = in && parent[idx3(x, y, z, a.nx, a.ny)] != kLiquid;
+        const uint64_t mask = __ballot(gas);
+        const uint64_t starts = mask & ~((mask << 1) & ~kRowStarts);
+        const int lane = li & 63;
+        const uint64_t upto = ~0ull >> (63 - lane);
+        lp[li] = gas ? (uint32_t)((li & ~63) + 63 - __clzll(starts & upto)) : kLiquid;
     }
     __syncthreads();
+    // links to other rows: two adjacent runs always have a link at which one end starts its run
+    // (the later-starting run's first node lies within the other's neighbourhood window, or the
+    // other's first node touches it), so only such links are united -- per run, not per node
+    auto starts_run = [&](int li, int lx) {
+        return lx == 0 || lds_load(lp + li - 1) == kLiquid;
+    };
     for (int li = threadIdx.x; li < NT; li += blockDim.x) {
         if (lds_load(lp + li) == kLiquid) continue;
         int lx, ly, lz, x, y, z;
         node(li, lx, ly, lz, x, y, z);
+        const bool s0 = starts_run(li, lx);
 #pragma unroll
         for (int h = 0; h < L::nhalf; ++h) {
             const int i = L::half[h];
+            if (L::ey[i] == 0 && L::ez[i] == 0) continue;  // along the row: the run
             if (!local_link<Q>(lx, ly, lz, x, y, z, i, a)) continue;
             const int lj = li + L::ex[i] + T::TX * (L::ey[i] + T::TY * L::ez[i]);
             if (lds_load(lp + lj) == kLiquid) continue;
+            if (!s0 && !starts_run(lj, lx + L::ex[i])) continue;
             lds_unite(lp, (uint32_t)li, (uint32_t)lj);
         }
     }

@@ -459,7 +459,8 @@ int upload_schedule(sc_sim* s)
 }
 
 // Ledger slots of this pass's bubbles: a fed bubble takes over what its nuclei are owed; an
-// unfed one leaves it with them.  Device layout: owed[nb], nodes[nb], gain[nb] (zero).
+// unfed one leaves it with them.  Device layout: owed[nb], nodes[nb], then gain (zero) with one
+// 128-byte line per bubble.
 int ledger_setup(sc_sim* s, const std::vector<int32_t>& feed)
 {
 #pragma clang fp contract(off)
@@ -467,7 +468,7 @@ int ledger_setup(sc_sim* s, const std::vector<int32_t>& feed)
     s->ledger_nb = nb;
     s->ledger_lead.assign((size_t)nb, -1);
     if (nb == 0) return SC_OK;
-    std::vector<double> host((size_t)3 * nb, 0.0);
+    std::vector<double> host((size_t)(2 + kLedgerGainStride) * nb, 0.0);
     for (int b = 0; b < nb; ++b) {
         s->ledger_lead[b] = s->bub[b].nucleus;
         host[(size_t)nb + b] = (double)s->bub[b].n;

@@ -170,6 +170,7 @@ struct MergeResult {
 // the lead (smallest) nucleus of each with its node's coordinates (the centroid anchor), the slot
 // of each bubble's root in slot_of_root, and zeroed statistics for k_stats.  One buffer of
 // bubble_tab_bytes(n) bytes holds every table; head[0] = nb, head[1] = candidate pairs found.
+constexpr int kStatStride = 16;
 struct BubbleTab {
     int32_t* head;
     uint32_t* comp;             // [n]
@@ -177,8 +178,11 @@ struct BubbleTab {
     int32_t* lead;              // [n]
     int32_t* first;             // [n] scratch: 1 for the smallest nucleus of each label
     int32_t* anchors;           // [3n]
-    unsigned long long* count;  // [n]
-    unsigned long long* sums;   // [3n]
+    // bubble b's node count at count[b * kStatStride] and its centroid sums at
+    // sums[b * kStatStride + c] (sums = count + 1): one 128-byte line per bubble, since every
+    // wave of a bubble's gas nodes adds to them atomically and atomics to one line serialize
+    unsigned long long* count;
+    unsigned long long* sums;
     double* cen;                // [3n]
     double* rad;                // [n]
 };
@@ -253,11 +257,15 @@ hipError_t launch_film(int q, int storage, const void* f, const uint32_t* labels
 // Blowing-agent source for one step: f_i(x) += w_i * T_b / n_b on the listed gas nodes, with
 // T_b = owed[b] + dm[b]; the stored values' exact gain closes the ledger (owed[b] = T_b - gain).
 // Device tables of nb bubble slots; gain (2^-40 fixed point) is zero between steps.
+// Bubble b's gain sits at gain[b * kLedgerGainStride]: one 128-byte line per bubble, since every
+// wave of a bubble's gas nodes adds to it atomically and atomics to one line serialize.
+constexpr int kLedgerGainStride = 16;
 struct SourceLedger {
     const double* dm;          // this step's release of each bubble's nuclei
     const double* nodes;       // n_b, gas nodes listed for the bubble
     double* owed;              // mass released earlier that the storage has not taken yet
-    unsigned long long* gain;  // sum of this step's gains in 2^-40 units (two's complement)
+    unsigned long long* gain;  // sum of this step's gains in 2^-40 units (two's complement),
+                               // at stride kLedgerGainStride
     int nb;
     uint64_t key;              // stochastic-rounding stream (16-bit storage)
 };

@@ -17,12 +17,15 @@ static dim3 grid_for(int64_t n)
     return dim3((unsigned)b);
 }
 
+// Coordinates of node n.  n < N <= 2^31 (sc_create bounds a population array to 2^32 bytes), so
+// 32-bit unsigned division is exact, at a fraction of the cost of 64-bit division.
 __device__ __forceinline__ void coords3(int64_t n, int nx, int ny, int& x, int& y, int& z)
 {
-    x = (int)(n % nx);
-    const int64_t r = n / nx;
-    y = (int)(r % ny);
-    z = (int)(r / ny);
+    const uint32_t m = (uint32_t)n;
+    const uint32_t r = m / (uint32_t)nx;
+    x = (int)(m - r * (uint32_t)nx);
+    y = (int)(r % (uint32_t)ny);
+    z = (int)(r / (uint32_t)ny);
 }
 
 __device__ __forceinline__ int64_t idx3(int x, int y, int z, int nx, int ny)
@@ -523,7 +526,10 @@ __global__ void __launch_bounds__(UnionTile<Q>::THREADS) k_union_local(uint32_t*
     }
 }
 
-// The links the tiles could not see: those that leave a tile or wrap around the box.
+// The links the tiles could not see: those that leave a tile or wrap around the box.  As inside
+// the tiles, only links at which one end starts its run along x (the first gas node of a tile
+// row, or one whose left neighbour is liquid) are united: an x-link across a tile face always
+// ends at such a node, and two adjacent runs of different rows always share such a link.
 template <int Q>
 __global__ void k_union_cross(uint32_t* parent, FieldArgs a)
 {
@@ -535,6 +541,7 @@ __global__ void k_union_cross(uint32_t* parent, FieldArgs a)
         int x, y, z;
         coords3(n, a.nx, a.ny, x, y, z);
         const int lx = x % T::TX, ly = y % T::TY, lz = z % T::TZ;
+        const bool s0 = lx == 0 || load_parent(parent, (uint32_t)(n - 1)) == kLiquid;
 #pragma unroll
         for (int h = 0; h < L::nhalf; ++h) {
             const int i = L::half[h];
@@ -542,6 +549,10 @@ __global__ void k_union_cross(uint32_t* parent, FieldArgs a)
             const int64_t m = shifted<Q>(x, y, z, i, +1, a);
             if (m == n) continue;
             if (load_parent(parent, (uint32_t)m) == kLiquid) continue;
+            if (!s0) {
+                const int mx = wrap_once(x + L::ex[i], a.nx);
+                if (mx % T::TX != 0 && load_parent(parent, (uint32_t)(m - 1)) != kLiquid) continue;
+            }
             unite(parent, (uint32_t)n, (uint32_t)m);
         }
     }
@@ -594,10 +605,11 @@ __global__ void k_stats(const uint32_t* labels, const int32_t* slot_of_root, con
         }
         // two's-complement wrap-around makes unsigned adds exact signed sums
         wave_add_by_key<4>(b, v, [&](int k, const long long* s) {
-            atomicAdd(count + k, (unsigned long long)s[0]);
-            atomicAdd(sums + 3 * k + 0, (unsigned long long)s[1]);
-            atomicAdd(sums + 3 * k + 1, (unsigned long long)s[2]);
-            atomicAdd(sums + 3 * k + 2, (unsigned long long)s[3]);
+            const size_t o = (size_t)k * kStatStride;
+            atomicAdd(count + o, (unsigned long long)s[0]);
+            atomicAdd(sums + o + 0, (unsigned long long)s[1]);
+            atomicAdd(sums + o + 1, (unsigned long long)s[2]);
+            atomicAdd(sums + o + 2, (unsigned long long)s[3]);
         });
     }
 }
@@ -896,13 +908,24 @@ __global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_sl
                 const int64_t n = list_node[k];
                 int x, y, z;
                 coords3(n, a.nx, a.ny, x, y, z);
+                // population i streams into n from n - e_i: 32-bit offsets per axis (indexed by
+                // e + 1), as in the step kernel
+                const uint32_t nx = a.nx, plane = (uint32_t)a.nx * (uint32_t)a.ny;
+                const uint32_t xo[3] = {(uint32_t)wrap_once(x + 1, a.nx), (uint32_t)x,
+                                        (uint32_t)wrap_once(x - 1, a.nx)};
+                const uint32_t yo[3] = {(uint32_t)wrap_once(y + 1, a.ny) * nx, (uint32_t)y * nx,
+                                        (uint32_t)wrap_once(y - 1, a.ny) * nx};
+                const uint32_t zo[3] = {(uint32_t)wrap_once(z + 1, a.nz) * plane,
+                                        (uint32_t)z * plane,
+                                        (uint32_t)wrap_once(z - 1, a.nz) * plane};
                 // every population of the node is loaded before any is stored (the stores
                 // would otherwise order each load behind the previous direction's store)
                 S* slot[Q];
                 S old[Q];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    slot[i] = f + (int64_t)i * a.N + shifted<Q>(x, y, z, i, -1, a);
+                    slot[i] = f + (int64_t)i * a.N +
+                              (xo[L::ex[i] + 1] + yo[L::ey[i] + 1] + zo[L::ez[i] + 1]);
                     old[i] = *slot[i];
                 }
                 double gain = 0.0;
@@ -920,7 +943,7 @@ __global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_sl
             }
         }
         wave_add_by_key<1>(b, gfx, [&](int kb, const long long* s) {
-            atomicAdd(&led.gain[kb], (unsigned long long)s[0]);
+            atomicAdd(&led.gain[(size_t)kb * kLedgerGainStride], (unsigned long long)s[0]);
         });
     }
 }
@@ -929,10 +952,10 @@ __global__ void k_source(S* f, const uint32_t* list_node, const int32_t* list_sl
 __global__ void __launch_bounds__(256) k_source_close(SourceLedger led)
 {
     for (int b = threadIdx.x; b < led.nb; b += blockDim.x) {
-        const long long g = (long long)led.gain[b];
+        const long long g = (long long)led.gain[(size_t)b * kLedgerGainStride];
         const double T = led.owed[b] + led.dm[b];
         led.owed[b] = T - (double)g * kGainUnit;
-        led.gain[b] = 0ull;
+        led.gain[(size_t)b * kLedgerGainStride] = 0ull;
     }
 }
 
@@ -1286,10 +1309,10 @@ __device__ void stage_out_body(const StageOut& o)
     if (o.head && t < 16) o.dst_head[t] = o.head[t];
     for (int k = t; k < o.n; k += blockDim.x) {
         o.dst_comp[k] = o.comp[k];
-        o.dst_count[k] = o.count[k];
-        o.dst_sums[3 * k + 0] = o.sums[3 * k + 0];
-        o.dst_sums[3 * k + 1] = o.sums[3 * k + 1];
-        o.dst_sums[3 * k + 2] = o.sums[3 * k + 2];
+        o.dst_count[k] = o.count[(size_t)k * kStatStride];
+        o.dst_sums[3 * k + 0] = o.sums[(size_t)k * kStatStride + 0];
+        o.dst_sums[3 * k + 1] = o.sums[(size_t)k * kStatStride + 1];
+        o.dst_sums[3 * k + 2] = o.sums[(size_t)k * kStatStride + 2];
     }
     for (int k = t; k < o.ledger_nb; k += blockDim.x) o.dst_owed[k] = o.owed[k];
     for (int k = t; k < o.npairs; k += blockDim.x) {
@@ -1314,8 +1337,8 @@ static size_t tab_align(size_t b) { return (b + 255) & ~size_t(255); }
 size_t bubble_tab_bytes(int n)
 {
     const size_t m = (size_t)(n > 0 ? n : 1);
-    return tab_align(64) + tab_align(4 * m) * 4 + tab_align(12 * m) + tab_align(8 * m) +
-           tab_align(24 * m) + tab_align(24 * m) + tab_align(8 * m);
+    return tab_align(64) + tab_align(4 * m) * 4 + tab_align(12 * m) +
+           tab_align(8 * kStatStride * m) + tab_align(24 * m) + tab_align(8 * m);
 }
 
 BubbleTab bubble_tab_view(void* base, int n)
@@ -1329,8 +1352,8 @@ BubbleTab bubble_tab_view(void* base, int n)
     t.lead = (int32_t*)p; p += tab_align(4 * m);
     t.first = (int32_t*)p; p += tab_align(4 * m);
     t.anchors = (int32_t*)p; p += tab_align(12 * m);
-    t.count = (unsigned long long*)p; p += tab_align(8 * m);
-    t.sums = (unsigned long long*)p; p += tab_align(24 * m);
+    t.count = (unsigned long long*)p; p += tab_align(8 * kStatStride * m);
+    t.sums = t.count + 1;
     t.cen = (double*)p; p += tab_align(24 * m);
     t.rad = (double*)p;
     return t;
@@ -1378,10 +1401,10 @@ __global__ void __launch_bounds__(1024) k_bubble_table(const uint32_t* labels,
         t.anchors[3 * b + 0] = (int32_t)(a0 % nx);
         t.anchors[3 * b + 1] = (int32_t)((a0 / nx) % ny);
         t.anchors[3 * b + 2] = (int32_t)(a0 / ((int64_t)nx * ny));
-        t.count[b] = 0ull;
-        t.sums[3 * b + 0] = 0ull;
-        t.sums[3 * b + 1] = 0ull;
-        t.sums[3 * b + 2] = 0ull;
+        t.count[(size_t)b * kStatStride] = 0ull;
+        t.sums[(size_t)b * kStatStride + 0] = 0ull;
+        t.sums[(size_t)b * kStatStride + 1] = 0ull;
+        t.sums[(size_t)b * kStatStride + 2] = 0ull;
         slot_of_root[c - 1] = b;
     }
     if (threadIdx.x == 0) {
@@ -1413,9 +1436,10 @@ __device__ void find_pairs(const BubbleTab& t, const int32_t* group, int dim, in
 #pragma clang fp contract(off)
     const int nb = t.head[0];
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const double n = (double)t.count[b];
+        const double n = (double)t.count[(size_t)b * kStatStride];
         for (int c = 0; c < 3; ++c)
-            t.cen[3 * b + c] = (double)t.anchors[3 * b + c] + (double)(long long)t.sums[3 * b + c] / n;
+            t.cen[3 * b + c] = (double)t.anchors[3 * b + c] +
+                               (double)(long long)t.sums[(size_t)b * kStatStride + c] / n;
         if (dim == 2) {
             t.cen[3 * b + 2] = 0.0;
             t.rad[b] = sqrt(n / M_PI);

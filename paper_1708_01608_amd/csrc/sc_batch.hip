@@ -299,6 +299,28 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
         }
     }
     __syncthreads();
+    // runs along x: a wave holds 64 consecutive nodes, so one ballot of the gas mask (and one of
+    // the row starts) gives every gas node the first node of its run within the wave's segment,
+    // which becomes its parent; a run that began before the segment (the node before it gas, in
+    // the same row: the carry into lane 0) continues from that node.  x-links then need no union,
+    // except the periodic one from x = nx - 1 to 0.
+    for (int n0 = t; n0 < ((N + 63) & ~63); n0 += kBatchThreads) {
+        const int lane = n0 & 63;
+        const int seg = n0 - lane;
+        const bool gas = n0 < N && ld_par(par, n0) != kNone;
+        const unsigned long long mask = __ballot(gas);
+        const unsigned long long rows = __ballot(n0 < N && n0 % nx == 0);
+        // gas stays gas while the wave before rewrites its parents, so this read is stable
+        const unsigned long long cin =
+            (seg > 0 && seg < N && seg % nx != 0 && ld_par(par, seg - 1) != kNone) ? 1ull : 0ull;
+        const unsigned long long starts = mask & ~(((mask << 1) | cin) & ~rows);
+        const unsigned long long upto = starts & (~0ull >> (63 - lane));
+        if (gas) par[n0] = upto ? (uint32_t)(seg + 63 - __clzll(upto)) : (uint32_t)(seg - 1);
+    }
+    __syncthreads();
+    // links to other rows: two adjacent runs always share a link at which one end starts its run
+    // (x = 0 counts as a start, so every link across the periodic boundary qualifies): only those
+    // are united, about one union per run instead of one per link
     constexpr int U2 = 8;
     for (int n0 = t; n0 < N; n0 += U2 * kBatchThreads) {
         // gas or liquid never changes in this pass: one mask bit per gas node of the group
@@ -313,11 +335,15 @@ __device__ bool batch_test(const float* f, uint32_t* par, const BatchInst& in, i
             gas &= gas - 1;
             const int n = n0 + u * kBatchThreads;
             const int x = n % nx, y = n / nx;
+            const bool s0 = x == 0 || ld_par(par, n - 1) == kNone;
 #pragma unroll
             for (int h = 0; h < L::nhalf; ++h) {
                 const int i = L::half[h];
-                const int m = wrap_once(x + L::ex[i], nx) + nx * wrap_once(y + L::ey[i], ny);
+                if (L::ey[i] == 0 && x != nx - 1) continue;  // inside the row: the run
+                const int mx = wrap_once(x + L::ex[i], nx);
+                const int m = mx + nx * wrap_once(y + L::ey[i], ny);
                 if (ld_par(par, m) == kNone) continue;
+                if (L::ey[i] != 0 && !s0 && mx != 0 && ld_par(par, m - 1) != kNone) continue;
                 batch_unite(par, (uint32_t)n, (uint32_t)m);
             }
         }

@@ -219,10 +219,50 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
         }
     }
 
+    // FP32 arithmetic: one plane per call, loading plane z+1 into `ld` and colliding plane z from
+    // `co`; two calls per iteration with the arrays' roles swapped, so no plane is copied
+    auto plane = [&](int z, float (&co)[19], float (&ld)[19], A& dco, A& dld) {
+        const int s = (z - z0 + 1) & 3;
+        const int sn = (s + 1) & 3, sp = (s + 3) & 3;
+        {
+            const int zn = wrap_once(z + 1, nz);
+            const int zm = wrap_once(zn - 1, nz), zp = wrap_once(zn + 1, nz);
+            if (own) {
+                pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, zn, zm, zp, ld);
+                dld = sum_dev<19, A>(ld);
+                ps[sn][ty + 1][tx + 1] = psi_f(c.rho_ref + dld);
+            }
+            if (ring) {
+                float h[19];
+                pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, zn, zm, zp, h);
+                ps[sn][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
+            }
+        }
+        __syncthreads();
+        if (own) {
+            const A pc = ps[s][ty + 1][tx + 1];
+            A fx, fy, fz;
+            interaction_sum<19, A>(
+                [&](int i) {
+                    const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
+                    return ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
+                },
+                fx, fy, fz);
+            const A gp = -c.G * pc;
+            collide_store<19, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), co, dco,
+                                            gp * fx, gp * fy, gp * fz, c);
+        }
+    };
+    if constexpr (!std::is_same<A, double>::value) {
+        for (int z = z0; z < ze; z += 2) {
+            plane(z, cur, nxt, dcur, dnxt);
+            if (z + 1 < ze) plane(z + 1, nxt, cur, dnxt, dcur);
+        }
+    } else {
     for (int z = z0; z < ze; ++z) {
         const int s = (z - z0 + 1) & 3;
         const int sn = (s + 1) & 3, sp = (s + 3) & 3;
-        if constexpr (std::is_same<A, double>::value) {
+        {
             // FP64 arithmetic fills the 128 VGPRs of a 1024-thread block, so the loop is shaped
             // for registers: every lane loads plane z+1 (a lane outside a ragged tile its clamped
             // in-box node, harmlessly) and the ring's loads and sum form one block, so both sets
@@ -271,42 +311,13 @@ __global__ void __launch_bounds__(TX* TY) k_step3d(const S* __restrict__ src, S*
                 collide_store<19, A, S, NT, EXT, true>(dst, N, (uint32_t)(ox + nx * (oy + ny * z)),
                                                       cur, dcur, gp * fx, gp * fy, gp * fz, c);
             }
-        } else {
-            {
-                const int zn = wrap_once(z + 1, nz);
-                const int zm = wrap_once(zn - 1, nz), zp = wrap_once(zn + 1, nz);
-                if (own) {
-                    pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, zn, zm, zp, nxt);
-                    dnxt = sum_dev<19, A>(nxt);
-                    ps[sn][ty + 1][tx + 1] = psi_f(c.rho_ref + dnxt);
-                }
-                if (ring) {
-                    float h[19];
-                    pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, zn, zm, zp, h);
-                    ps[sn][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(h));
-                }
-            }
-            __syncthreads();
-            if (own) {
-                const A pc = ps[s][ty + 1][tx + 1];
-                A fx, fy, fz;
-                interaction_sum<19, A>(
-                    [&](int i) {
-                        const int slot = L::ez[i] > 0 ? sn : (L::ez[i] < 0 ? sp : s);
-                        return ps[slot][ty + 1 + L::ey[i]][tx + 1 + L::ex[i]];
-                    },
-                    fx, fy, fz);
-                const A gp = -c.G * pc;
-                collide_store<19, A, S, NT, EXT>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur,
-                                                dcur, gp * fx, gp * fy, gp * fz, c);
-            }
         }
 #pragma unroll
         for (int i = 0; i < 19; ++i) cur[i] = nxt[i];
         dcur = dnxt;
     }
+    }
 }
-
 // ------------------------------------------------------------------------------------------
 // D3Q19, software-pipelined: the loads of plane z+2 are issued before plane z is collided, so a
 // wave keeps a plane of loads in flight through its collision and stores.  Ring nodes go to the
@@ -360,7 +371,7 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
     const int hym = wrap_once(hy - 1, ny), hyp = wrap_once(hy + 1, ny);
 
     float cur[19], nxt[19], pre[19], hpre[19];
-    A dcur = (A)0, dnxt = (A)0;
+    A dcur = (A)0, dnxt = (A)0, dpre = (A)0;
 
     // planes z0-1 (psi), z0 (psi + cur), z0+1 (psi + nxt)
 #pragma unroll 1
@@ -388,14 +399,17 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
     }
     __syncthreads();
 
-    for (int z = z0; z < ze; ++z) {
+    // one plane per call: plane z+2's loads into `pf`, plane z collided from `co`, plane z+1
+    // waiting in `nx1`; three calls per iteration with the arrays' roles rotated, so no plane
+    // is copied
+    auto plane = [&](int z, float (&co)[19], float (&pf)[19], A& dco, A& dpf) {
         const int s = (z - z0 + 1) & 3;
         const int sn = (s + 1) & 3, sp = (s + 3) & 3, s2 = (s + 2) & 3;
         const bool more = z + 1 < ze;  // plane z+2 is needed by the collision of plane z+1
         if (more) {
             const int z2 = wrap_once(z + 2 >= nz ? z + 2 - nz : z + 2, nz);
             const int zm = wrap_once(z2 - 1, nz), zp = wrap_once(z2 + 1, nz);
-            if (own) pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z2, zm, zp, pre);
+            if (own) pull_node<19>(src, N, nx, ny, x, xm, xp, y, ym, yp, z2, zm, zp, pf);
             if (ring) pull_node<19>(src, N, nx, ny, hx, hxm, hxp, hy, hym, hyp, z2, zm, zp, hpre);
         }
         if (own) {
@@ -408,25 +422,22 @@ __global__ void __launch_bounds__(TX* TY) k_step3d_pipe(const S* __restrict__ sr
                 },
                 fx, fy, fz);
             const A gp = -c.G * pc;
-            collide_store<19, A, S, true>(dst, N, (uint32_t)(x + nx * (y + ny * z)), cur, dcur,
+            collide_store<19, A, S, true>(dst, N, (uint32_t)(x + nx * (y + ny * z)), co, dco,
                                           gp * fx, gp * fy, gp * fz, c);
         }
-        A dpre = (A)0;
         if (more) {
             if (own) {
-                dpre = sum_dev<19, A>(pre);
-                ps[s2][ty + 1][tx + 1] = psi_f(c.rho_ref + dpre);
+                dpf = sum_dev<19, A>(pf);
+                ps[s2][ty + 1][tx + 1] = psi_f(c.rho_ref + dpf);
             }
             if (ring) ps[s2][hly][hlx] = psi_f(c.rho_ref + sum_dev<19, A>(hpre));
         }
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            cur[i] = nxt[i];
-            nxt[i] = pre[i];
-        }
-        dcur = dnxt;
-        dnxt = dpre;
+    };
+    for (int z = z0; z < ze; z += 3) {
+        plane(z, cur, pre, dcur, dpre);
+        if (z + 1 < ze) plane(z + 1, nxt, cur, dnxt, dcur);
+        if (z + 2 < ze) plane(z + 2, pre, nxt, dpre, dnxt);
     }
 }
 

@@ -317,19 +317,28 @@ def precision_measure(args):
     """The precision pattern on the 512^3 foam (D3Q19, 400 nuclei, tau 0.9, K 50): the step kernel
     with FP32 storage (FP64 and FP32 arithmetic) against FP16 and BF16 shifted storage (FP32
     arithmetic), each timed over `precision_steps` bench steps after one untimed."""
+    from paper_1708_01608_amd import sc
+
     spec = workload_spec("foam_3d_large")
     rows = {}
+    march = {}
     for storage, compute in (("f32", "f64"), ("f32", "f32"), ("f16", "f32"), ("bf16", "f32")):
         r = run_gpu(spec, args, storage, compute, args.precision_steps, 1)
         b = bytes_per_node(spec.q, storage) * spec.N
         avg_s = r["step_ms"] / 1e3 / max(r["launches"], 1)
+        # the storage type's own memory pattern, marched with the run's tiles, no arithmetic
+        key = (storage, tuple(r["tile"][:3]))
+        if key not in march:
+            march[key] = sc.pattern_probe(spec.nx, spec.ny, spec.nz, storage, key[1], 3)[1]
         rows[f"{storage} storage / {compute} compute"] = {
             "MLUPS": round(spec.N * args.precision_steps * spec.K / r["wall"] / 1e6, 1),
             "stencil_only_MLUPS": round(spec.N / avg_s / 1e6, 1),
             "bytes_per_node": bytes_per_node(spec.q, storage),
             "avg_launch_us": round(avg_s * 1e6, 1),
             "achieved_GBps": round(b / avg_s / 1e9, 1),
-            "frac": round(b / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac": round(b / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+            "pattern_march_GBps": round(march[key], 1),
+            "frac_of_pattern_march": round(b / avg_s / 1e9 / march[key], 4)}
     return spec, rows
 
 

@@ -101,9 +101,9 @@ __device__ __forceinline__ void interaction_sum(P psi, A& sx, A& sy, A& sz)
     }
 }
 
-// 1/rho: FP64 through the hardware reciprocal and two Newton steps (each doubles the correct
-// bits: a faithful result for the densities here, at half the cost of IEEE division); FP32 as
-// the compiler divides.
+// 1/rho through the hardware reciprocal and Newton steps (each doubles the correct bits): two
+// in FP64, a faithful result for the densities here at half the cost of IEEE division; one in
+// FP32 (3 instructions instead of the 10 of IEEE division, within an ulp).
 __device__ __forceinline__ double recip(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -112,7 +112,11 @@ __device__ __forceinline__ double recip(double x)
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
-__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
 
 // Deviation sum sum_i g_i in the arithmetic type A (fixed order: the ring and the owner of a
 // node obtain the same value).

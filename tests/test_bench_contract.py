@@ -73,6 +73,13 @@ def test_bench_prints_the_contract_line():
     ro = d["roofline"]
     assert ro["bound"] == "hbm" and ro["unit"] == "GB/s" and ro["peak"] == 8000.0
     assert abs(ro["frac"] - ro["achieved"] / ro["peak"]) < 1e-3
+    # the measured ceilings: a plain copy, and the step's own memory pattern with its arithmetic
+    # left out (flat and marching the step's tiles); the step cannot move data much faster than
+    # the marching pattern it is built on
+    for k in ("measured_copy_GBps", "measured_pattern_flat_GBps", "measured_pattern_march_GBps"):
+        assert ro[k] > 0, k
+    assert abs(ro["frac_of_pattern_march"] - ro["achieved"] / ro["measured_pattern_march_GBps"]) < 1e-3
+    assert ro["frac_of_pattern_march"] < 1.2
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
     # the two system patterns of the metric ride on the same line
@@ -80,6 +87,7 @@ def test_bench_prints_the_contract_line():
     for k in ("f32 storage / f64 compute", "f16 storage / f32 compute",
               "bf16 storage / f32 compute"):
         assert pr["runs"][k]["MLUPS"] > 0 and 0 < pr["runs"][k]["frac"] < 1
+        assert pr["runs"][k]["pattern_march_GBps"] > 0
         assert pr["error_vs_fp64"][k]["rho"] >= 0
     assert pr["error_vs_fp64"]["f32 storage / f64 compute"]["rho"] <= 1e-5
     ba = d["batching"]

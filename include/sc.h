@@ -383,9 +383,9 @@ int sc_hbm_probe(size_t bytes, int32_t reps, double* copy_GBps, double* read_GBp
  * freed on return; the null stream).  flat_GBps: one node per thread; march_GBps: blocks of
  * tile_x * tile_y (<= 1024) threads, each a tile_x x tile_y tile marching tile_z planes in
  * the step kernel's block order.  Best of `reps` timed launches after one untimed, as read +
- * written bytes per second.  SC_E_INVAL for a bad box (ny, nz <= 65535; N elements of at
- * most 2^32 bytes per direction), tile, storage or reps; SC_E_DEVICE or the allocation's
- * error otherwise. */
+ * written bytes per second.  SC_E_INVAL for a bad box (nx <= 2^30, ny, nz <= 65535; N
+ * elements of at most 2^32 bytes per direction), tile, storage or reps; SC_E_DEVICE or the
+ * allocation's error otherwise. */
 int sc_pattern_probe(int32_t nx, int32_t ny, int32_t nz, int32_t storage, int32_t tile_x,
                      int32_t tile_y, int32_t tile_z, int32_t reps, double* flat_GBps,
                      double* march_GBps);

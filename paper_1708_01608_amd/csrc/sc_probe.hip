@@ -86,7 +86,8 @@ __global__ void __launch_bounds__(1024) k_pattern_march(const T* __restrict__ s,
                                                         T* __restrict__ d, int nx, int ny, int nz,
                                                         int tx, int ty, int tz)
 {
-    const int gx = (nx + tx - 1) / tx, gy = (ny + ty - 1) / ty, gz = (nz + tz - 1) / tz;
+    const int gx = (int)(((int64_t)nx + tx - 1) / tx), gy = (int)(((int64_t)ny + ty - 1) / ty),
+              gz = (int)(((int64_t)nz + tz - 1) / tz);
     const int nb = gx * gy * gz;
     const int b = (nb % 8 == 0) ? (int)(blockIdx.x & 7) * (nb >> 3) + (int)(blockIdx.x >> 3)
                                 : (int)blockIdx.x;
@@ -163,7 +164,7 @@ extern "C" int sc_pattern_probe(int32_t nx, int32_t ny, int32_t nz, int32_t stor
         return set_error(SC_E_INVAL, "pattern probe: bad box, tile, storage or reps");
     const int64_t N = (int64_t)nx * ny * nz;
     const size_t es = storage == SC_STORE_F32 ? 4 : 2;
-    if ((size_t)N * es > ((size_t)1 << 32) || ny > 65535 || nz > 65535)
+    if ((size_t)N * es > ((size_t)1 << 32) || nx > (1 << 30) || ny > 65535 || nz > 65535)
         return set_error(SC_E_INVAL, "pattern probe: box too large");
     const size_t bytes = 19 * (size_t)N * es;
     void *a = nullptr, *b = nullptr;
@@ -174,8 +175,9 @@ extern "C" int sc_pattern_probe(int32_t nx, int32_t ny, int32_t nz, int32_t stor
             rc = set_error(SC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
         return e == hipSuccess;
     };
-    const int64_t tiles = (int64_t)((nx + tile_x - 1) / tile_x) * ((ny + tile_y - 1) / tile_y) *
-                          ((nz + tile_z - 1) / tile_z);
+    const int64_t tiles = (((int64_t)nx + tile_x - 1) / tile_x) *
+                          (((int64_t)ny + tile_y - 1) / tile_y) *
+                          (((int64_t)nz + tile_z - 1) / tile_z);
     if (tiles > 0x7fffffff) return set_error(SC_E_INVAL, "pattern probe: too many tiles");
     if (ck(hipMalloc(&a, bytes), "hipMalloc") && ck(hipMalloc(&b, bytes), "hipMalloc") &&
         ck(hipMemset(a, 0, bytes), "memset") && ck(hipEventCreate(&e0), "event") &&
@@ -185,7 +187,8 @@ extern "C" int sc_pattern_probe(int32_t nx, int32_t ny, int32_t nz, int32_t stor
             for (int r = 0; r <= reps && rc == SC_OK; ++r) {
                 ck(hipEventRecord(e0, 0), "record");
                 if (which == 0) {
-                    const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)ny, (unsigned)nz);
+                    const dim3 grid((unsigned)(((int64_t)nx + 255) / 256), (unsigned)ny,
+                                    (unsigned)nz);
                     if (es == 4)
                         hipLaunchKernelGGL(k_pattern_flat<uint32_t>, grid, dim3(256), 0, 0,
                                            (const uint32_t*)a, (uint32_t*)b, nx, ny, nz);

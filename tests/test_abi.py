@@ -276,10 +276,12 @@ def test_binding_refuses_overlapping_outputs():
 @pytest.mark.parametrize("args", [
     (0, 8, 8, 0, 8, 8, 4, 1), (8, 8, 8, 3, 8, 8, 4, 1), (8, 8, 8, 0, 64, 32, 4, 1),
     (8, 8, 8, 0, 8, 8, 0, 1), (8, 8, 8, 0, 8, 8, 4, 0),
+    ((1 << 30) + 1, 1, 1, 1, 256, 1, 1, 1), (8, 65536, 1, 1, 8, 8, 1, 1),
+    (1025, 1024, 1024, 0, 256, 4, 64, 1),
 ])
 def test_pattern_probe_arguments_are_checked(lib, args):
     # rejected before any device call: empty box, unknown storage, tile above 1024 threads or
-    # without planes, no timed repetition
+    # without planes, no timed repetition, an axis too long, more than 2^32 bytes per direction
     f, m = C.c_double(-1.0), C.c_double(-1.0)
     assert lib.sc_pattern_probe(*args, C.byref(f), C.byref(m)) == sc.SC_E_INVAL
     assert f.value == -1.0 and m.value == -1.0

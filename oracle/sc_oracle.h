@@ -24,9 +24,10 @@
  *
  * Pins: every function below is checked by the test suite against something other than
  * itself (closed forms, conservation laws, brute force, the coexistence and Laplace laws, the
- * spinodal sign rule of the criterion).  Parity unpinned: the merge and topological steps that
- * a run produces (and, with the barrier, whether a film holds), because the paper prints no
- * merge time or film profile to compare with; they are compared only GPU against oracle.
+ * spinodal sign rule of the criterion).  The merge and topological steps a run produces are
+ * pinned by the lattice's symmetries (a translated or rotated box gives the same run moved
+ * with it) and by film-thickness ordering; their values themselves have no reference, because
+ * the paper prints no merge time or film profile, and are compared GPU against oracle.
  */
 #ifndef SC_ORACLE_H
 #define SC_ORACLE_H

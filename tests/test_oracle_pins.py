@@ -578,3 +578,87 @@ def test_two_bubble_mirror_symmetry():
     assert np.abs(r - r[::-1, :]).max() < 1e-13
     assert np.abs(ux + ux[:, ::-1]).max() < 1e-13
     assert np.abs(uy + uy[::-1, :]).max() < 1e-13
+
+
+# ------------------------------------------------------------------------------------------
+# P14: merge dynamics (Fig. 1 steps 7-9, Sec. 4).  The paper prints no merge time or film
+# profile, so the merge steps a run produces are pinned by what the lattice fixes: a periodic
+# box translated, or the D2Q9 lattice rotated by 90 degrees, gives the same run moved with it
+# (translation exactly; the rotation permutes the directions, so the sums round in another
+# order), and a thinner film ruptures sooner.  A slip in the film walk's axes or wrap, in the
+# labels' node order or in the pair selection breaks one of these.
+# ------------------------------------------------------------------------------------------
+def _two_bubble_merge(gap=4, shift=(0, 0), transpose=False, barrier=False, steps=2500):
+    spec = W.two_bubble(amp=0.0, gap=gap)
+    n = spec.nx
+    c = spec.centres.copy()
+    if transpose:
+        c = c[:, [1, 0, 2]]
+    c[:, 0] = (c[:, 0] + shift[0]) % n
+    c[:, 1] = (c[:, 1] + shift[1]) % n
+    o = OracleSim(9, n, n, 1, spec.tau, spec.G, spec.rho_l, spec.rho_g, 0.0, spec.seed, 0.0,
+                  spec.K, spec.film_max, barrier=barrier)
+    o.seed_nuclei(c, spec.radii, spec.budgets, 0.0)
+    while o.t < steps and not o.topo_events():
+        o.step(spec.K)
+    return o
+
+
+_MERGE_BASE = {}
+
+
+def _merge_base():
+    if "o" not in _MERGE_BASE:
+        _MERGE_BASE["o"] = _two_bubble_merge()
+    return _MERGE_BASE["o"]
+
+
+def _node_xy(n, nx=128):
+    return n % nx, n // nx
+
+
+def test_merge_events_move_with_a_translated_box():
+    a = _merge_base()
+    b = _two_bubble_merge(shift=(60, 21))
+    ea, eb = a.events(), b.events()
+    assert len(ea) == 1 and len(eb) == 1
+    assert eb[0]["step"] == ea[0]["step"] and eb[0]["film_len"] == ea[0]["film_len"]
+    assert eb[0]["lap_p"] == ea[0]["lap_p"] and eb[0]["rho_film"] == ea[0]["rho_film"]
+    xa, ya = _node_xy(ea[0]["film_node"])
+    assert _node_xy(eb[0]["film_node"]) == ((xa + 60) % 128, (ya + 21) % 128)
+    assert [e["step"] for e in b.topo_events()] == [e["step"] for e in a.topo_events()]
+    ra = a.fields()[0].reshape(128, 128)
+    rb = b.fields()[0].reshape(128, 128)
+    assert np.array_equal(np.roll(ra, (21, 60), axis=(0, 1)), rb)
+
+
+def test_merge_events_turn_with_a_rotated_lattice():
+    a = _merge_base()
+    b = _two_bubble_merge(transpose=True)
+    ea, eb = a.events(), b.events()
+    assert len(eb) == 1 and eb[0]["step"] == ea[0]["step"]
+    assert abs(eb[0]["lap_p"] / ea[0]["lap_p"] - 1.0) < 1e-9
+    xa, ya = _node_xy(ea[0]["film_node"])
+    assert _node_xy(eb[0]["film_node"]) == (ya, xa)
+    assert [e["step"] for e in b.topo_events()] == [e["step"] for e in a.topo_events()]
+
+
+def test_thinner_films_rupture_sooner():
+    # criterion steps: gap 3 < gap 4 (which fires, then the bubbles touch); gap 5 holds past
+    # the same horizon
+    t4 = _merge_base().events()[0]["step"]
+    o3 = _two_bubble_merge(gap=3)
+    o5 = _two_bubble_merge(gap=5, steps=2000)
+    assert o3.events() and o3.events()[0]["step"] < t4
+    assert not o5.events() and not o5.topo_events()
+
+
+def test_barrier_run_moves_with_a_translated_box():
+    # the modified Shan-Chen barrier (owners, coronas, the substituted psi) under translation
+    a = _two_bubble_merge(barrier=True, steps=600)
+    b = _two_bubble_merge(barrier=True, shift=(60, 21), steps=600)
+    ra = a.fields()[0].reshape(128, 128)
+    rb = b.fields()[0].reshape(128, 128)
+    assert np.array_equal(np.roll(ra, (21, 60), axis=(0, 1)), rb)
+    assert np.array_equal(np.roll(a.owner().reshape(128, 128), (21, 60), axis=(0, 1)),
+                          b.owner().reshape(128, 128))

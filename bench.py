@@ -75,6 +75,9 @@ def workload_spec(name):
             "mixture_3d": W.mixture_3d, "gas_rich_3d": W.gas_rich_3d}[name]()
 
 
+METRIC_FULL = ("Shan-Chen MLUPS & % of HBM roofline; FP16-store/batched vs FP32 at fixed err")
+
+
 def bytes_per_node(q, storage, components=1):
     """Algorithmic bytes per node and step: every population read once and written once."""
     return components * 2 * q * (4 if storage == "f32" else 2)
@@ -505,6 +508,9 @@ def main():
             "batched_vs_one_by_one": (round(bm["mlups"] / bm["one_by_one"], 1)
                                       if bm["one_by_one"] else None),
         }
+        # the line now carries both halves of the metric: the FP32 roofline and the 16-bit /
+        # batched forms against plain FP32 with their stated errors
+        out["metric"] = METRIC_FULL
     if not args.no_cpu_baseline:
         out["cpu_baseline"], errors = cpu_baseline_leg(spec, args.cpu_sample_steps, err_spec,
                                                        err_steps, err_fields)

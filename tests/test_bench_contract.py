@@ -70,6 +70,8 @@ def test_bench_prints_the_contract_line():
         assert k in d, k
     assert d["n_gpus"] == 1 and d["steps"] == 1 and d["value"] > 0
     assert d["config"]["workload"] == "foam_3d"
+    assert d["metric"] == ("Shan-Chen MLUPS & % of HBM roofline; FP16-store/batched vs FP32 at "
+                           "fixed err")
     ro = d["roofline"]
     assert ro["bound"] == "hbm" and ro["unit"] == "GB/s" and ro["peak"] == 8000.0
     assert abs(ro["frac"] - ro["achieved"] / ro["peak"]) < 1e-3

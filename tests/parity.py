@@ -12,8 +12,10 @@ from paper_1708_01608_amd import sc
 # Reported, not gated: FP32 arithmetic, FP16 and BF16 storage.  Their errors are printed by the
 # tests and stated beside their speed; the bounds in SANITY only reject a broken kernel (a wrong
 # sign, index or storage shift blows the fields up to O(1) relative error and beyond), they make
-# no precision claim.  For scale: FP32 arithmetic measured up to 1.7e-4 (rho) / 8e-5 (u), FP16 up
-# to 6e-3 / 0.37 and BF16 up to 7.5e-2 / 1.37 on the two-bubble box at t = 100.
+# no precision claim.  For scale, at t = 100: FP32 arithmetic up to 1.7e-5 (rho, a ragged 3D box
+# with the source) and 5.0e-5 (u, the 128^3 foam error run); on the two-bubble box FP16 6.8e-3 /
+# 0.36 and BF16 6.6e-2 / 1.40; the largest 16-bit errors, with gravity or the barrier, FP16
+# 1.0e-2 / 0.34 and BF16 8.0e-2 / 1.58.
 RHO_TOL = 1e-5
 U_TOL = 1e-5
 GATED = {("f32", "f64"): (RHO_TOL, U_TOL)}

@@ -237,6 +237,29 @@ def test_foam_3d_full_size_all_nodes():
         g.close()
 
 
+def test_foam_3d_large_full_size_all_nodes_after_4_steps():
+    # the 512^3 precision workload (400 nuclei, their source every step) in the benchmark's
+    # launch configuration for FP32 storage (tuned shapes: tiles marching up to 512 planes), every
+    # node against the oracle after 4 steps; the oracle's 134 M-node steps bound the horizon
+    spec = W.foam_3d_large()
+    _announce("foam_3d_large 512^3 4 steps, every node (oracle ~5-10 s/step)")
+    o = oracle_from_spec(spec)
+    for _ in range(4):
+        o.step(1)
+        print(f"oracle t = {o.t}", flush=True)
+    for compute in ("f64", "f32"):
+        g = gpu_from_spec(spec, compute=compute)
+        print(f"gpu {compute}: step shape {g.step_config()}", flush=True)
+        g.step(4)
+        e_rho, e_u, tg, to = field_errors(g, o)
+        check_errors("f32", compute, e_rho, e_u, "full-size 512^3 t=4")
+        assert abs(tg[0] / to[0] - 1) < 1e-7
+        _, rem_g = g.nuclei(len(spec.radii))
+        np.testing.assert_array_equal(rem_g, o.nuclei()[1])  # FP64 budgets, same order
+        g.close()
+    del o
+
+
 def test_foam_3d_error_run_16bit_storage():
     """128^3 box of the 512^3 precision workload: error of every storage type at t = 100."""
     spec = W.foam_3d_error_run()

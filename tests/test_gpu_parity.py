@@ -383,6 +383,57 @@ def test_foam_3d_large_full_size_conservation(storage):
     g.close()
 
 
+def test_largest_box_fp32_storage():
+    """The largest box: 1024^3 D3Q19 with FP32 storage puts 2^32 bytes in each direction's array,
+    all that the step's 32-bit byte offsets address.  A nucleus across the periodic corner (the
+    far end of every array and its wrap to the start) in a noiseless liquid, after 4 steps: the
+    corner's neighbourhood equals the oracle's 32^3 box with the same nucleus (in 4 steps a
+    disturbance spreads less than 12 nodes, so neither box can tell its size), and every other
+    node is still the uniform liquid (the same density bit for bit, velocity zero)."""
+    import torch
+
+    n, m, steps, reach = 1024, 32, 4, 12
+    mk = lambda b: W.SimSpec(name=f"corner{b}", q=19, nx=b, ny=b, nz=b, tau=0.9, K=0, amp=0.0,
+                             centres=np.array([(b - 0.5, b - 0.5, b - 0.5)]),
+                             radii=np.array([3.0]), budgets=np.zeros(1), rate=0.0)
+    _announce(f"largest box {n}^3 FP32 storage, {steps} steps")
+    small = oracle_from_spec(mk(m))
+    small.step(steps)
+    ro, uo, _ = small.fields()
+    ro = ro.reshape(m, m, m)
+    uo = uo.reshape(3, m, m, m)
+    g = gpu_from_spec(mk(n))
+    t0 = g.totals()
+    g.step(steps)
+    t1 = g.totals()
+    rg, ug, _ = g.fields()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    print(f"mass {t1[0] / t0[0] - 1:.2e}", flush=True)
+    assert abs(t1[0] / t0[0] - 1) < 1e-7
+    rg = rg.reshape(n, n, n)
+    ug = ug.reshape(3, n, n, n)
+    near = np.r_[0:reach, m - reach:m]          # small-box coordinates around the corner
+    big = np.r_[0:reach, n - reach:n]           # the same nodes in the big box
+    rs, rb = ro[np.ix_(near, near, near)], rg[np.ix_(big, big, big)]
+    e_rho = float(np.max(np.abs(rb - rs) / rs))
+    us = uo[np.ix_(range(3), near, near, near)]
+    ub = ug[np.ix_(range(3), big, big, big)]
+    e_u = float(np.max(np.abs(ub - us)) / np.max(np.abs(us)))
+    check_errors("f32", "f64", e_rho, e_u, "corner of the 1024^3 box")
+    # beyond the corner's reach the liquid is untouched; the uniform value in FP32 storage
+    far = rg[reach:n - reach, :, :]
+    rho_l = float(rg[n // 2, n // 2, n // 2])
+    assert abs(rho_l - 1.93) < 1e-6
+    assert float(np.max(np.abs(far - rho_l))) == 0.0
+    # u there is zero up to FP64 rounding of the reported velocity (a misplaced store would show
+    # as a density or velocity of the order of the stored populations)
+    u_far = float(np.max(np.abs(ug[:, reach:n - reach, :, :])))
+    print(f"far field: rho uniform, max |u| {u_far:.2e}", flush=True)
+    assert u_far < 1e-12
+
+
 # ---- determinism, state round trip, error latching ---------------------------------------------
 def test_runs_are_bitwise_deterministic():
     spec = W.two_bubble()

@@ -1,5 +1,6 @@
 """GPU parity at the edges of the input space: the smallest boxes the library accepts, boxes one
-node-row thin against the tile, and runs without any nucleus."""
+node-row thin against the tile, runs without any nucleus, and the method's degenerate cases (no
+interaction, a nucleus on no node, a nucleus filling the box, two nuclei at one centre)."""
 import numpy as np
 import pytest
 
@@ -134,3 +135,74 @@ def test_bandwidth_probes_report_rates(storage):
     assert copy_gbs > 0 and read_gbs > 0
     flat, march = sc.pattern_probe(70, 40, 30, storage, (32, 8, 7), 2)
     assert np.isfinite(flat) and np.isfinite(march) and flat > 0 and march > 0
+
+
+# ---- degenerate cases of the method ------------------------------------------------------------
+def _degenerate(q, shape, centres, radii, G=-5.0, amp=1e-3):
+    nx, ny, nz = shape
+    n = len(radii)
+    return W.SimSpec(name="degenerate", q=q, nx=nx, ny=ny, nz=nz, tau=0.9, G=G, amp=amp, seed=7,
+                     K=10, centres=np.asarray(centres, float).reshape(n, 3),
+                     radii=np.asarray(radii, float), budgets=np.full(n, 1e-2), rate=1e-4)
+
+
+def _check_degenerate(spec, steps=40):
+    g, o, e_rho, e_u, tg, to = _compare(spec, steps)
+    assert e_rho <= RHO_TOL and _u_ok(e_u, U_TOL)
+    assert _mass_ok(spec, steps, tg, to)
+    assert np.array_equal(g.last_labels(), o.labels())
+    n = len(spec.radii)
+    if n:
+        cg, rg = g.nuclei(n)
+        co, ro = o.nuclei()
+        assert np.array_equal(cg, co)
+        np.testing.assert_array_equal(rg, ro)  # FP64 budgets, same order
+    assert events_key(g.merge_events()) == events_key(o.events())
+    return g, o
+
+
+_DEG_BOXES = [(9, (40, 30, 1)), (19, (20, 16, 12))]
+
+
+@pytest.mark.parametrize("q,shape", _DEG_BOXES)
+def test_no_interaction(q, shape):
+    # G = 0: the Shan-Chen force vanishes and the step is plain BGK; a gas nucleus then simply
+    # diffuses into the liquid
+    c = [(shape[0] / 2, shape[1] / 2, shape[2] / 2 if q == 19 else 0.0)]
+    spec = _degenerate(q, shape, c, [4.0], G=0.0)
+    _announce(f"degenerate: G = 0, q={q} {shape}")
+    _check_degenerate(spec)
+
+
+@pytest.mark.parametrize("q,shape", _DEG_BOXES)
+def test_nucleus_covering_no_node(q, shape):
+    # a nucleus smaller than the distance to the nearest node paints nothing: it belongs to no
+    # gas component, so nothing is released for it and its budget stays whole
+    c = [(10.5, 10.5, 6.5 if q == 19 else 0.0), (3.0, 4.0, 2.0 if q == 19 else 0.0)]
+    spec = _degenerate(q, shape, c, [0.3, 2.5])
+    _announce(f"degenerate: nucleus on no node, q={q} {shape}")
+    g, o = _check_degenerate(spec)
+    assert g.nuclei(2)[0][0] == 0 and g.nuclei(2)[1][0] == spec.budgets[0]
+
+
+@pytest.mark.parametrize("q,shape", _DEG_BOXES)
+def test_nucleus_filling_the_box(q, shape):
+    # a nucleus larger than the box: every node is gas, one component across every periodic
+    # seam, and the agent feeds the whole box
+    c = [(1.0, 2.0, 3.0 if q == 19 else 0.0)]
+    spec = _degenerate(q, shape, c, [1000.0])
+    _announce(f"degenerate: nucleus filling the box, q={q} {shape}")
+    g, o = _check_degenerate(spec)
+    assert len(np.unique(g.last_labels())) == 1 and g.last_labels()[0] == 1
+
+
+@pytest.mark.parametrize("q,shape,radius", [(9, (40, 30, 1), 5.0), (19, (24, 20, 20), 6.0)])
+def test_two_nuclei_at_one_centre(q, shape, radius):
+    # two nuclei painted over each other: one bubble that holds both, whose release pools the
+    # two budgets (the 3D bubble is larger, so that it outlives the run)
+    c = [(12.0, 9.0, 10.0 if q == 19 else 0.0)] * 2
+    spec = _degenerate(q, shape, c, [radius, 3.0])
+    _announce(f"degenerate: two nuclei at one centre, q={q} {shape}")
+    g, o = _check_degenerate(spec)
+    comp, _ = g.nuclei(2)
+    assert comp[0] == comp[1] != 0
